@@ -1,0 +1,137 @@
+/*
+ * Exact Euclidean DBSCAN on one AMD Instinct MI355X (gfx950): C ABI.
+ *
+ * The operation is the DBSCAN problem of Wang, Gu and Shun, "Theoretically-Efficient
+ * and Practical Parallel DBSCAN" (SIGMOD 2020), section "Preliminaries", computed by
+ * the grid method of the paper's Algorithm 1: cells of side eps/sqrt(d) (section
+ * "Grid Computation"), MarkCore (Algorithm 2), ClusterCore with bichromatic-closest-
+ * pair cell connectivity and a lock-free union-find (Algorithm 3 and section
+ * "Cluster Core"), and ClusterBorder (Algorithm 4).
+ *
+ * Output contract (exact; identical on every call for the same input):
+ *   - core_flags[i] = 1 iff at least min_pts points p_j (p_i included) satisfy
+ *     D(p_i, p_j) <= E2, else 0;
+ *   - cluster_id[i] for a core point = the smallest index of a core point in its
+ *     cluster; for a non-core point = the smallest cluster id among core points
+ *     within eps (the paper lets such a point belong to several clusters), or -1
+ *     (noise) when there is none;
+ *   where D(p, q) = (((0 + t_0*t_0) + t_1*t_1) + ...), t_k = p_k - q_k, every step a
+ *   float64 operation rounded to nearest-even, summed in dimension order with no
+ *   fused multiply-add, and E2 = eps*eps rounded once.  No square root is taken.
+ *
+ * Pointers named "device" must be device memory of the context's GPU (for example
+ * from hipMalloc or a PyTorch CUDA tensor).  The caller owns every input and output
+ * buffer; the library keeps no reference to them after the stream work of the call.
+ * Calls are asynchronous on `stream` (a hipStream_t; NULL = the default stream).
+ * A context must not be used by two host threads at once, and two calls on one
+ * context must not run concurrently on different streams (they share scratch).
+ *
+ * Return codes: 0 on success, otherwise one of DBSCAN_E*.  Argument errors are
+ * reported synchronously.  Data-dependent errors (non-finite coordinates) are
+ * detected on the GPU; dbscan_get_stats() returns them after synchronising the
+ * stream.  Outputs are undefined when an error occurs.  Any finite input is
+ * accepted: when the cell grid would need more than 64 Morton key bits the key is
+ * coarsened by a power of two (key_shift) and the float64 diameter guard splits
+ * the resulting large cells, so the result is unchanged (only slower).
+ */
+#ifndef PAPER_1912_06255_DBSCAN_H
+#define PAPER_1912_06255_DBSCAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBSCAN_OK 0
+#define DBSCAN_EINVAL (-1)     /* bad argument: n<0, d not in [1,8], eps not finite or <= 0,
+                                  min_pts < 1, NULL pointer with n > 0, n > DBSCAN_MAX_N */
+#define DBSCAN_ENOMEM (-2)     /* device scratch could not be allocated */
+#define DBSCAN_EHIP (-3)       /* a HIP runtime call failed */
+#define DBSCAN_ENONFINITE (-4) /* a coordinate is NaN or infinite */
+#define DBSCAN_EINTERNAL (-5)  /* an internal bounded wait expired (should not happen) */
+
+#define DBSCAN_MAX_N 1073741823LL /* 2^30 - 1 points per call */
+#define DBSCAN_MAX_D 8
+
+/* Distance arithmetic of the pairwise decisions.  Both modes return identical
+ * outputs: DBSCAN_FP32_FILTER decides most pairs from float32 cell-local
+ * coordinates with a proven error band and re-decides in float64 the pairs whose
+ * float32 result falls inside the band. */
+#define DBSCAN_PLAIN_FP64 0
+#define DBSCAN_FP32_FILTER 1
+
+typedef struct dbscan_ctx dbscan_ctx;
+
+/* Counters of the last completed call on a context. */
+typedef struct {
+  int64_t n_points;      /* n of the call */
+  int64_t n_cells;       /* non-empty cells after splitting unsafe ones */
+  int64_t n_unsafe;      /* grid cells whose float64 diameter test failed (split) */
+  int64_t n_core;        /* core points */
+  int64_t bcp_calls;     /* cell pairs that reached a closest-pair test */
+  int64_t uf_links;      /* successful union-find links */
+  int64_t fp64_rechecks; /* pairs re-decided in float64 (FP32 filter mode) */
+  int32_t key_bits;      /* bits of the Morton cell key */
+  int32_t key_shift;     /* key coordinate = floor(cell index / 2^key_shift) */
+  uint32_t status;       /* 0 or a bit set of DBSCAN_STATUS_* */
+  uint32_t reserved;
+} dbscan_stats;
+
+#define DBSCAN_STATUS_NONFINITE 1u
+#define DBSCAN_STATUS_WAIT_EXPIRED 4u
+
+/* Create a context bound to HIP device `device`.  *out receives the handle. */
+int dbscan_ctx_create(dbscan_ctx **out, int device);
+
+/* Free a context and its device scratch.  Synchronises the device first. */
+int dbscan_ctx_destroy(dbscan_ctx *ctx);
+
+/*
+ * Exact DBSCAN of one point cloud (paper, Algorithm 1).
+ *   points      device, float64 [n][d] row-major (point i at points + i*d)
+ *   n, d        number of points (0 allowed) and dimension (1..8)
+ *   eps         radius, finite and > 0
+ *   min_pts     density threshold >= 1 (the point itself counts)
+ *   mode        DBSCAN_PLAIN_FP64 or DBSCAN_FP32_FILTER
+ *   core_flags  device, uint8 [n] output
+ *   cluster_id  device, int32 [n] output
+ *   stream      hipStream_t or NULL
+ * Scratch grows inside the context on demand (a synchronous allocation the first
+ * time a larger n is seen); dbscan_reserve() does it ahead of time.
+ */
+int dbscan(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d, double eps,
+           int32_t min_pts, int32_t mode, uint8_t *core_flags, int32_t *cluster_id,
+           void *stream);
+
+/* Pre-size the context's scratch for clouds of up to n points of dimension d. */
+int dbscan_reserve(dbscan_ctx *ctx, int64_t n, int32_t d);
+
+/*
+ * Synchronise `stream` and copy the counters and status of the last call into
+ * *out.  Returns DBSCAN_ENONFINITE / DBSCAN_EINTERNAL when the call hit that
+ * condition, else DBSCAN_OK.
+ */
+int dbscan_get_stats(dbscan_ctx *ctx, void *stream, dbscan_stats *out);
+
+/*
+ * Phase timing.  With profiling on, each call records HIP events on its stream
+ * between its phases (grid box, keys, radix sort, cell runs, cell boxes and
+ * guard, box tree, MarkCore, core counts, ClusterCore, relabel, ClusterBorder,
+ * output scatter).  dbscan_phase_times() synchronises `stream` and writes up to
+ * `cap` per-phase durations in milliseconds of the last call; it returns the
+ * number of phases (DBSCAN_NUM_PHASES) or a negative error code.
+ */
+#define DBSCAN_NUM_PHASES 12
+int dbscan_set_profiling(dbscan_ctx *ctx, int on);
+int dbscan_phase_times(dbscan_ctx *ctx, void *stream, float *ms, int32_t cap);
+const char *dbscan_phase_name(int32_t phase);
+
+/* Static description of a return code. */
+const char *dbscan_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_1912_06255_DBSCAN_H */

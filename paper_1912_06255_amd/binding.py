@@ -1,0 +1,186 @@
+"""Thin ctypes binding of the HIP library (include/dbscan.h).
+
+Only argument marshalling happens here: PyTorch provides device memory and the
+stream, every step of the computation runs in the library's kernels.  If the
+shared library is missing this module raises; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdbscan_hip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dbscan.h")
+
+OK = 0
+EINVAL = -1
+ENOMEM = -2
+EHIP = -3
+ENONFINITE = -4
+EINTERNAL = -5
+
+PLAIN_FP64 = 0
+FP32_FILTER = 1
+MODES = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "fp32_filter": FP32_FILTER, "filter": FP32_FILTER}
+
+
+class DbscanError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64),
+        ("n_cells", ctypes.c_int64),
+        ("n_unsafe", ctypes.c_int64),
+        ("n_core", ctypes.c_int64),
+        ("bcp_calls", ctypes.c_int64),
+        ("uf_links", ctypes.c_int64),
+        ("fp64_rechecks", ctypes.c_int64),
+        ("key_bits", ctypes.c_int32),
+        ("key_shift", ctypes.c_int32),
+        ("status", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+_ctx: dict[int, ctypes.c_void_p] = {}
+
+
+def load():
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1912_06255_amd.build`"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.dbscan_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.dbscan_ctx_destroy.argtypes = [vp]
+    lib.dbscan_reserve.argtypes = [vp, i64, i32]
+    lib.dbscan.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp]
+    lib.dbscan_get_stats.argtypes = [vp, vp, ctypes.POINTER(Stats)]
+    lib.dbscan_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.dbscan_phase_times.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.dbscan_phase_name.argtypes = [i32]
+    lib.dbscan_phase_name.restype = ctypes.c_char_p
+    lib.dbscan_strerror.argtypes = [ctypes.c_int]
+    lib.dbscan_strerror.restype = ctypes.c_char_p
+    for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
+              "dbscan_set_profiling", "dbscan_phase_times"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/dbscan.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dbscan\w*)\s*\(", text, flags=re.M)))
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().dbscan_strerror(code).decode()
+    except Exception:  # pragma: no cover - only used in messages
+        return "error"
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise DbscanError(rc, what)
+
+
+def context(device: int = 0) -> ctypes.c_void_p:
+    """The per-process context of a device (created on first use)."""
+    with _lock:
+        if device not in _ctx:
+            h = ctypes.c_void_p()
+            _check(load().dbscan_ctx_create(ctypes.byref(h), device), "dbscan_ctx_create")
+            _ctx[device] = h
+        return _ctx[device]
+
+
+def reserve(n: int, d: int, device: int = 0) -> None:
+    _check(load().dbscan_reserve(context(device), int(n), int(d)), "dbscan_reserve")
+
+
+def _stream_handle(device, stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None, check: bool = True):
+    """Exact DBSCAN of ``points`` (float64 CUDA tensor [n, d]).
+
+    Returns ``(core uint8[n], cluster_id int32[n])`` on the same device.  With
+    ``check`` the stream is synchronised and device-detected errors raise
+    ``DbscanError``; without it the call stays asynchronous.
+    """
+    import torch
+
+    if not (isinstance(points, torch.Tensor) and points.is_cuda):
+        raise TypeError("points must be a CUDA (HIP) tensor")
+    if points.dtype != torch.float64 or points.dim() != 2:
+        raise TypeError("points must be float64 of shape [n, d]")
+    points = points.contiguous()
+    n, d = points.shape
+    dev = points.device.index if points.device.index is not None else torch.cuda.current_device()
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    if out is None:
+        core = torch.empty(n, dtype=torch.uint8, device=points.device)
+        label = torch.empty(n, dtype=torch.int32, device=points.device)
+    else:
+        core, label = out
+    sh = _stream_handle(dev, stream)
+    rc = load().dbscan(
+        context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
+        ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(label.data_ptr()), sh,
+    )
+    _check(rc, "dbscan")
+    if check and n > 0:
+        stats(dev, stream, raise_on_error=True)
+    return core, label
+
+
+def stats(device: int = 0, stream=None, raise_on_error: bool = False) -> dict:
+    """Synchronise the stream and return the counters of the last call."""
+    st = Stats()
+    rc = load().dbscan_get_stats(context(device), _stream_handle(device, stream), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc, "dbscan (device)")
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def set_profiling(on: bool, device: int = 0) -> None:
+    _check(load().dbscan_set_profiling(context(device), 1 if on else 0), "dbscan_set_profiling")
+
+
+def phase_times(device: int = 0, stream=None) -> dict:
+    """Per-phase milliseconds of the last call (profiling must be on)."""
+    lib = load()
+    buf = (ctypes.c_float * 32)()
+    k = lib.dbscan_phase_times(context(device), _stream_handle(device, stream), buf, 32)
+    if k < 0:
+        raise DbscanError(k, "dbscan_phase_times")
+    return {lib.dbscan_phase_name(i).decode(): float(buf[i]) for i in range(k)}

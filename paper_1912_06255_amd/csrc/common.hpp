@@ -1,0 +1,212 @@
+// Device-side building blocks shared by the DBSCAN kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DB_DEV __device__ __forceinline__
+
+namespace db {
+
+constexpr int kWave = 64;
+constexpr int kMaxD = 8;
+constexpr int kTreeLevels = 5;  // node levels above the cells; 64^6 cells max
+
+// ---------------------------------------------------------------------------
+// Device-resident state of one call, written by the kernels themselves so that no
+// host read is needed between phases.
+// ---------------------------------------------------------------------------
+struct GridDesc {
+  double origin[kMaxD];   // per-dimension minimum of the points
+  double side;            // cell side s = eps / sqrt(d), rounded
+  int32_t bits[kMaxD];    // bits of each cell coordinate in the Morton key
+  int32_t total_bits;     // sum of bits
+  int32_t shift;          // key coordinate = floor(q / 2^shift), q = cell index
+  int32_t passes;         // 8-bit radix passes needed
+  uint32_t epoch;         // bumped once per call; tags look-back words
+  uint32_t status;        // DBSCAN_STATUS_* bits
+  int32_t n_cells;        // C before/after splitting
+  int32_t n_unsafe;       // cells whose float64 diameter test failed
+  int32_t n_core;
+  unsigned long long bcp_calls;
+  unsigned long long uf_links;
+  unsigned long long rechecks;
+};
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+DB_DEV int lane_id() { return __lane_id(); }
+
+DB_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+DB_DEV uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+DB_DEV int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Orders LDS traffic between lanes of one wave.
+DB_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+DB_DEV int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+DB_DEV int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+DB_DEV int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+DB_DEV int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+DB_DEV uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+DB_DEV double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+DB_DEV double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Coherent (L2, device scope) loads and stores for data other waves update.
+// ---------------------------------------------------------------------------
+template <class T>
+DB_DEV T ld_acq(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+DB_DEV void st_rel(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DB_DEV void atomic_min_double(double* addr, double v) {
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(addr);
+  unsigned long long old = ld_acq(a);
+  while (v < __longlong_as_double((long long)old)) {
+    unsigned long long prev = atomicCAS(a, old, (unsigned long long)__double_as_longlong(v));
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
+DB_DEV void atomic_max_double(double* addr, double v) {
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(addr);
+  unsigned long long old = ld_acq(a);
+  while (v > __longlong_as_double((long long)old)) {
+    unsigned long long prev = atomicCAS(a, old, (unsigned long long)__double_as_longlong(v));
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The float64 distance decision: t_k = p_k - q_k, acc = acc + t_k*t_k in dimension
+// order, each operation rounded once (the library is built with
+// -ffp-contract=off; the pragma keeps it so if that flag is ever dropped).
+// ---------------------------------------------------------------------------
+template <int D>
+DB_DEV double sqdist(const double (&p)[D], const double (&q)[D]) {
+#pragma clang fp contract(off)
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double t = p[k] - q[k];
+    acc = acc + t * t;
+  }
+  return acc;
+}
+
+// Lower bound of D(p, q) over p in box [alo, ahi] and q in box [blo, bhi].
+// Rounding is monotone, so the rounded per-dimension gap is at most |fl(p_k - q_k)|
+// for every such pair, and squares and sums preserve the order: a box distance
+// above E2 proves every pair between the boxes is farther than eps.
+template <int D>
+DB_DEV double box_sqdist(const double (&alo)[D], const double (&ahi)[D], const double* blo,
+                         const double* bhi, int stride, int j) {
+#pragma clang fp contract(off)
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double l = blo[(size_t)k * stride + j];
+    const double h = bhi[(size_t)k * stride + j];
+    double t = 0.0;
+    if (alo[k] > h) t = alo[k] - h;
+    else if (l > ahi[k]) t = l - ahi[k];
+    acc = acc + t * t;
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back: each tile publishes a 64-bit word
+//   [epoch:30 | flag:2 | value:32]
+// flag 1 = tile aggregate only, flag 2 = inclusive prefix.  Words whose epoch is
+// not the current call's count as "not yet published", so the state array never
+// needs clearing.  The wait is bounded; on expiry the status bit is raised and the
+// partial sum is used (the call then reports DBSCAN_EINTERNAL).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
+constexpr int kSpinLimit = 1 << 22;
+
+DB_DEV uint64_t lb_word(uint32_t epoch, uint64_t flag, uint32_t value) {
+  return ((uint64_t)(epoch & 0x3fffffffu) << 34) | (flag << 32) | value;
+}
+
+DB_DEV uint32_t lookback_exclusive(uint64_t* state, int stride, int tile, uint32_t epoch,
+                                   uint32_t* status) {
+  uint32_t excl = 0;
+  int j = tile - 1;
+  int spins = 0;
+  const uint32_t ep = epoch & 0x3fffffffu;
+  while (j >= 0) {
+    uint64_t w = ld_acq(&state[(size_t)j * stride]);
+    const uint32_t wep = (uint32_t)(w >> 34);
+    const uint64_t flag = (w >> 32) & 3;
+    if (wep != ep || flag == 0) {
+      if (++spins > kSpinLimit) {
+        atomicOr(status, 4u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)w;
+    if (flag == kFlagIncl) break;
+    --j;
+  }
+  return excl;
+}
+
+}  // namespace db

@@ -1,0 +1,331 @@
+// Host side of the C ABI declared in include/dbscan.h: context, scratch layout and
+// the launch sequence of one exact DBSCAN call (paper, Algorithm 1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/dbscan.h"
+#include "cluster.hpp"
+
+using namespace db;
+
+struct dbscan_ctx {
+  int device = 0;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  GridDesc* desc = nullptr;  // lives at the start of scratch, survives growth
+  size_t desc_bytes = 0;
+  int64_t last_n = 0;
+  bool profile = false;
+  bool events_ready = false;
+  bool events_recorded = false;
+  hipEvent_t ev[DBSCAN_NUM_PHASES + 1];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Bump layout of the per-call arrays inside the scratch block.  The same function
+// sizes the allocation (base = nullptr) and carves the pointers.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off = align_up(off + sizeof(T) * (size_t)(count > 0 ? count : 1));
+    return p;
+  }
+};
+
+size_t layout(char* base, int64_t n, int d, Work* W) {
+  Work tmp;
+  Work& w = W ? *W : tmp;
+  Carver c{base};
+  const int64_t tiles = ceil_div(n, kTile);
+  w.bbox_part = c.take<double>((int64_t)kBBoxBlocks * 2 * kMaxD);
+  w.ghist = c.take<uint32_t>(8 * 256);
+  w.tilectr = c.take<uint32_t>(16);
+  w.lbstate = c.take<uint64_t>(tiles * 256);
+  w.keyA = c.take<uint64_t>(n);
+  w.keyB = c.take<uint64_t>(n);
+  w.idxA = c.take<uint32_t>(n);
+  w.idxB = c.take<uint32_t>(n);
+  w.X = c.take<double>(n * d);
+  w.perm = c.take<int32_t>(n);
+  w.cellOf = c.take<int32_t>(n);
+  w.cellStart = c.take<int32_t>(n + 1);
+  w.cellOf2 = c.take<int32_t>(n);
+  w.cellStart2 = c.take<int32_t>(n + 1);
+  w.unsafe = c.take<uint8_t>(n);
+  int64_t cap = n;
+  for (int l = 0; l <= kTreeLevels; ++l) {
+    if (l > 0) cap = ceil_div(cap, 64);
+    w.tree.cap[l] = (int)cap;
+    w.tree.lo[l] = c.take<double>(cap * d);
+    w.tree.hi[l] = c.take<double>(cap * d);
+  }
+  w.coreS = c.take<uint8_t>(n);
+  w.coreCount = c.take<int32_t>(n);
+  w.parent = c.take<int32_t>(n);
+  w.minIdx = c.take<int32_t>(n);
+  w.cellLabel = c.take<int32_t>(n);
+  w.blabel = c.take<int32_t>(n);
+  return c.off;
+}
+
+int grow(dbscan_ctx* ctx, int64_t n, int d) {
+  const size_t need = ctx->desc_bytes + layout(nullptr, n, d, nullptr);
+  if (need <= ctx->scratch_bytes) return DBSCAN_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess) return DBSCAN_EHIP;
+  void* p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess) return DBSCAN_ENOMEM;
+  // keep the descriptor (and its epoch counter) across growth
+  if (ctx->scratch) {
+    if (hipMemcpy(p, ctx->scratch, ctx->desc_bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+      (void)hipFree(p);
+      return DBSCAN_EHIP;
+    }
+    (void)hipFree(ctx->scratch);
+  }
+  ctx->scratch = p;
+  ctx->scratch_bytes = need;
+  ctx->desc = reinterpret_cast<GridDesc*>(p);
+  return DBSCAN_OK;
+}
+
+unsigned grid_for(int64_t items, int per_block, unsigned cap) {
+  int64_t b = ceil_div(items, per_block);
+  if (b < 1) b = 1;
+  return (unsigned)(b > cap ? cap : b);
+}
+
+const char* const kPhaseNames[DBSCAN_NUM_PHASES] = {
+    "bbox", "keys", "radix_sort", "cells", "cell_boxes", "tree", "markcore",
+    "core_count", "cluster_core", "relabel", "border", "scatter"};
+
+struct Marks {
+  hipEvent_t* ev;  // null when profiling is off
+  hipStream_t s;
+  void operator()(int i) const {
+    if (ev) (void)hipEventRecord(ev[i], s);
+  }
+};
+
+template <int D>
+int run(const Work& W, hipStream_t s, const Marks& mark) {
+  const int64_t n = W.n;
+  const unsigned gp = grid_for(n, kBlock, 2048);           // one thread per point
+  const unsigned gw = grid_for(n, kWavesPerBlock, 4096);   // one wave per cell
+  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);  // wave per chunk
+  const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
+  const unsigned tiles = (unsigned)ceil_div(n, kTile);
+
+  mark(0);
+  k_init<<<1, kBlock, 0, s>>>(W);
+  k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W);
+  k_bbox_final<D><<<1, kWave, 0, s>>>(W, (int)nb);
+  mark(1);
+  k_keys<D><<<gp, kBlock, 0, s>>>(W);
+  mark(2);
+  for (int pass = 0; pass < 8; ++pass) k_sort_pass<<<tiles, kBlock, 0, s>>>(W, pass, (int)tiles);
+  mark(3);
+  k_cells<D><<<tiles, kBlock, 0, s>>>(W, 0);
+  mark(4);
+  k_cell_box_init<D><<<gp, kBlock, 0, s>>>(W, 0);
+  k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 0);
+  k_cell_safe<D><<<gp, kBlock, 0, s>>>(W);
+  // cells that fail the float64 diameter guard become singletons
+  k_cells<D><<<tiles, kBlock, 0, s>>>(W, 1);
+  k_cells_copy<<<gp, kBlock, 0, s>>>(W);
+  k_cell_box_init<D><<<gp, kBlock, 0, s>>>(W, 1);
+  k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 1);
+  mark(5);
+  for (int l = 1; l <= kTreeLevels; ++l) {
+    const int64_t nodes = W.tree.cap[l];
+    k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
+  }
+  mark(6);
+  k_markcore<D><<<gw, kBlock, 0, s>>>(W);
+  mark(7);
+  k_core_count<<<gp, kBlock, 0, s>>>(W);
+  mark(8);
+  k_bcp<D><<<gw, kBlock, 0, s>>>(W);
+  mark(9);
+  k_relabel_min<<<gc, kBlock, 0, s>>>(W);
+  k_cell_label<<<gp, kBlock, 0, s>>>(W);
+  mark(10);
+  k_border<D><<<gw, kBlock, 0, s>>>(W);
+  mark(11);
+  k_scatter<<<gp, kBlock, 0, s>>>(W);
+  mark(12);
+  return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbscan_ctx_create(dbscan_ctx** out, int device) {
+  if (!out) return DBSCAN_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return DBSCAN_EHIP;
+  if (device < 0 || device >= count) return DBSCAN_EINVAL;
+  dbscan_ctx* c = new (std::nothrow) dbscan_ctx();
+  if (!c) return DBSCAN_ENOMEM;
+  c->device = device;
+  c->desc_bytes = align_up(sizeof(GridDesc));
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return DBSCAN_EHIP;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, c->desc_bytes) != hipSuccess) {
+    delete c;
+    return DBSCAN_ENOMEM;
+  }
+  if (hipMemset(p, 0, c->desc_bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(p);
+    delete c;
+    return DBSCAN_EHIP;
+  }
+  c->scratch = p;
+  c->scratch_bytes = c->desc_bytes;
+  c->desc = reinterpret_cast<GridDesc*>(p);
+  *out = c;
+  return DBSCAN_OK;
+}
+
+int dbscan_ctx_destroy(dbscan_ctx* ctx) {
+  if (!ctx) return DBSCAN_EINVAL;
+  int rc = DBSCAN_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) rc = DBSCAN_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess) rc = DBSCAN_EHIP;
+  if (ctx->scratch && hipFree(ctx->scratch) != hipSuccess) rc = DBSCAN_EHIP;
+  if (ctx->events_ready)
+    for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+  return rc;
+}
+
+int dbscan_reserve(dbscan_ctx* ctx, int64_t n, int32_t d) {
+  if (!ctx || n < 0 || n > DBSCAN_MAX_N || d < 1 || d > DBSCAN_MAX_D) return DBSCAN_EINVAL;
+  return grow(ctx, n, d);
+}
+
+int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+           int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
+           void* stream) {
+  if (!ctx || n < 0 || n > DBSCAN_MAX_N || d < 1 || d > DBSCAN_MAX_D) return DBSCAN_EINVAL;
+  if (!(eps > 0.0) || !std::isfinite(eps) || min_pts < 1) return DBSCAN_EINVAL;
+  if (mode != DBSCAN_PLAIN_FP64) return DBSCAN_EINVAL;
+  if (n == 0) {
+    ctx->last_n = 0;
+    return DBSCAN_OK;
+  }
+  if (!points || !core_flags || !cluster_id) return DBSCAN_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  int rc = grow(ctx, n, d);
+  if (rc != DBSCAN_OK) return rc;
+
+  Work W;
+  std::memset(static_cast<void*>(&W), 0, sizeof(W));
+  W.n = (int)n;
+  W.minPts = min_pts;
+  W.E2 = eps * eps;
+  W.side = eps / std::sqrt((double)d);
+  W.pts = points;
+  W.core_out = core_flags;
+  W.label_out = cluster_id;
+  W.desc = ctx->desc;
+  layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
+
+  ctx->last_n = n;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->profile && !ctx->events_ready) {
+    for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i)
+      if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return DBSCAN_EHIP;
+    ctx->events_ready = true;
+  }
+  const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
+  ctx->events_recorded = ctx->profile;
+  switch (d) {
+    case 1: return run<1>(W, s, mark);
+    case 2: return run<2>(W, s, mark);
+    case 3: return run<3>(W, s, mark);
+    case 4: return run<4>(W, s, mark);
+    case 5: return run<5>(W, s, mark);
+    case 6: return run<6>(W, s, mark);
+    case 7: return run<7>(W, s, mark);
+    case 8: return run<8>(W, s, mark);
+  }
+  return DBSCAN_EINVAL;
+}
+
+int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
+  if (!ctx || !out) return DBSCAN_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DBSCAN_EHIP;
+  GridDesc g;
+  if (hipMemcpy(&g, ctx->desc, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return DBSCAN_EHIP;
+  std::memset(out, 0, sizeof(*out));
+  out->n_cells = g.n_cells;
+  out->n_unsafe = g.n_unsafe;
+  out->n_core = g.n_core;
+  out->bcp_calls = (int64_t)g.bcp_calls;
+  out->uf_links = (int64_t)g.uf_links;
+  out->fp64_rechecks = (int64_t)g.rechecks;
+  out->n_points = ctx->last_n;
+  out->key_bits = g.total_bits;
+  out->key_shift = g.shift;
+  out->status = g.status;
+  if (g.status & DBSCAN_STATUS_NONFINITE) return DBSCAN_ENONFINITE;
+  if (g.status & DBSCAN_STATUS_WAIT_EXPIRED) return DBSCAN_EINTERNAL;
+  return DBSCAN_OK;
+}
+
+int dbscan_set_profiling(dbscan_ctx* ctx, int on) {
+  if (!ctx) return DBSCAN_EINVAL;
+  ctx->profile = on != 0;
+  return DBSCAN_OK;
+}
+
+int dbscan_phase_times(dbscan_ctx* ctx, void* stream, float* ms, int32_t cap) {
+  if (!ctx || !ms || cap < 0) return DBSCAN_EINVAL;
+  if (!ctx->events_recorded) return DBSCAN_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DBSCAN_EHIP;
+  for (int i = 0; i < DBSCAN_NUM_PHASES && i < cap; ++i) {
+    if (hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]) != hipSuccess) return DBSCAN_EHIP;
+  }
+  return DBSCAN_NUM_PHASES;
+}
+
+const char* dbscan_phase_name(int32_t phase) {
+  return phase >= 0 && phase < DBSCAN_NUM_PHASES ? kPhaseNames[phase] : "";
+}
+
+const char* dbscan_strerror(int code) {
+  switch (code) {
+    case DBSCAN_OK: return "ok";
+    case DBSCAN_EINVAL: return "invalid argument";
+    case DBSCAN_ENOMEM: return "device scratch allocation failed";
+    case DBSCAN_EHIP: return "HIP runtime error";
+    case DBSCAN_ENONFINITE: return "non-finite coordinate";
+    case DBSCAN_EINTERNAL: return "internal bounded wait expired";
+  }
+  return "unknown error";
+}
+
+}  // extern "C"

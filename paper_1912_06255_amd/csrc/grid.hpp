@@ -1,0 +1,561 @@
+// Grid construction (paper: section "Grid Computation"; Algorithm 1, Cells):
+// bounding box, Morton cell keys, LSD radix sort of (key, index), cell runs with a
+// float64 diameter guard, and a 64-ary bounding-box tree over the sorted cells that
+// plays the role of the paper's k-d tree over cells (section "Finding Neighboring
+// Cells"): it returns exactly the non-empty cells that can hold a point within eps.
+#pragma once
+
+#include "common.hpp"
+
+namespace db {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSortItems = 8;
+constexpr int kTile = kBlock * kSortItems;  // keys per radix / scan tile
+
+// Look-back epoch slots within one call: 0..7 radix passes, 8..9 cell scans.
+constexpr uint32_t kEpochSlots = 16;
+
+struct TreeView {
+  const double* lo[kTreeLevels + 1];  // level 0 = cells, SoA [D][cap]
+  const double* hi[kTreeLevels + 1];
+  int cap[kTreeLevels + 1];
+};
+
+// All device pointers of one call.  Point and cell arrays use stride n (C <= n).
+struct Work {
+  int n;
+  int minPts;
+  double E2;
+  double side;
+  const double* pts;  // input, [n][D]
+  uint8_t* core_out;
+  int32_t* label_out;
+
+  GridDesc* desc;
+  double* bbox_part;  // [kBBoxBlocks][2*kMaxD]
+  uint32_t* ghist;    // [8][256]
+  uint32_t* tilectr;  // [16]
+  uint64_t* lbstate;  // [tiles * 256]
+  uint64_t* keyA;
+  uint64_t* keyB;
+  uint32_t* idxA;
+  uint32_t* idxB;
+  double* X;          // [D][n] points in cell order
+  int32_t* perm;      // sorted position -> input index
+  int32_t* cellOf;    // [n]
+  int32_t* cellStart; // [n+1]
+  int32_t* cellOf2;
+  int32_t* cellStart2;
+  uint8_t* unsafe;    // [n] per cell
+  TreeView tree;      // tree.lo[0] / hi[0] = cell boxes
+  uint8_t* coreS;     // [n] core flag, cell order
+  int32_t* coreCount; // [n] per cell
+  int32_t* parent;    // [n] union-find over cells
+  int32_t* minIdx;    // [n] per root: smallest input index of a core point
+  int32_t* cellLabel; // [n] per cell: cluster id of its core points or -1
+  int32_t* blabel;    // [n] border label, cell order
+};
+
+constexpr int kBBoxBlocks = 512;
+
+DB_DEV uint32_t epoch_of(const GridDesc* desc, uint32_t slot) {
+  return (desc->epoch * kEpochSlots + slot) & 0x3fffffffu;
+}
+
+// ---------------------------------------------------------------------------
+// Call initialisation: counters, histograms and the epoch.
+// ---------------------------------------------------------------------------
+__global__ void k_init(Work W) {
+  const int t = threadIdx.x;
+  for (int i = t; i < 8 * 256; i += blockDim.x) W.ghist[i] = 0;
+  if (t < 16) W.tilectr[t] = 0;
+  if (t == 0) {
+    GridDesc* g = W.desc;
+    g->epoch = g->epoch + 1;
+    g->status = 0;
+    g->n_cells = 0;
+    g->n_unsafe = 0;
+    g->n_core = 0;
+    g->bcp_calls = 0;
+    g->uf_links = 0;
+    g->rechecks = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1: bounding box (partials per block, then one block finalises the grid).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
+  __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
+  double lo[D], hi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    lo[k] = __builtin_inf();
+    hi[k] = -__builtin_inf();
+  }
+  bool bad = false;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double v = W.pts[(size_t)i * D + k];
+      bad |= !__builtin_isfinite(v);
+      lo[k] = fmin(lo[k], v);
+      hi[k] = fmax(hi[k], v);
+    }
+  }
+  if (bad) atomicOr(&W.desc->status, 1u);
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = wave_min(lo[k]), b = wave_max(hi[k]);
+    if (lane_id() == 0) {
+      s_lo[w][k] = a;
+      s_hi[w][k] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    const int k = threadIdx.x;
+    double a = s_lo[0][k], b = s_hi[0][k];
+    for (int j = 1; j < kWavesPerBlock; ++j) {
+      a = fmin(a, s_lo[j][k]);
+      b = fmax(b, s_hi[j][k]);
+    }
+    W.bbox_part[blockIdx.x * 2 * kMaxD + k] = a;
+    W.bbox_part[blockIdx.x * 2 * kMaxD + kMaxD + k] = b;
+  }
+}
+
+// Grid: origin o = min corner, q_k = floor((x_k - o_k) / s).  The Morton key holds
+// c_k = floor(q_k / 2^shift) with the smallest shift that fits all dimensions in
+// 64 bits; shift = 0 (cells of side s) unless the extent is extreme.  A coarser
+// key only makes cells larger: the diameter guard then splits them into single
+// points, so the result is unchanged.
+template <int D>
+__global__ void k_bbox_final(Work W, int nparts) {
+  if (threadIdx.x != 0) return;
+  GridDesc* g = W.desc;
+  const bool bad = (g->status & 1u) != 0;
+  int len[D];
+  int total = 0;
+  for (int k = 0; k < D; ++k) {
+    double a = __builtin_inf(), b = -__builtin_inf();
+    for (int j = 0; j < nparts; ++j) {
+      a = fmin(a, W.bbox_part[j * 2 * kMaxD + k]);
+      b = fmax(b, W.bbox_part[j * 2 * kMaxD + kMaxD + k]);
+    }
+    g->origin[k] = bad ? 0.0 : a;
+    len[k] = 0;
+    if (!bad) {
+      const double qmax = floor((b - a) / W.side);
+      if (!(qmax < 1e308)) len[k] = 1100;          // infinite extent ratio
+      else if (qmax >= 1.0) len[k] = ilogb(qmax) + 1;  // bit length of qmax
+    }
+    total += len[k];
+  }
+  int shift = 0;
+  for (;;) {
+    int t = 0;
+    for (int k = 0; k < D; ++k) t += max(0, len[k] - shift);
+    if (t <= 64) {
+      total = t;
+      break;
+    }
+    ++shift;
+  }
+  for (int k = 0; k < kMaxD; ++k) g->bits[k] = k < D ? max(0, len[k] - shift) : 0;
+  g->side = W.side;
+  g->shift = shift;
+  g->total_bits = total;
+  g->passes = (total + 7) / 8;
+}
+
+// ---------------------------------------------------------------------------
+// Morton key of every point and the 8-bit digit histograms of all radix passes.
+// ---------------------------------------------------------------------------
+template <int D>
+DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)[D], int maxb) {
+  unsigned long long c[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double q = floor(ldexp(floor((x[k] - g->origin[k]) / g->side), -g->shift));
+    const unsigned long long lim = bits[k] >= 64 ? ~0ull : ((1ull << bits[k]) - 1ull);
+    unsigned long long v = q > 0.0 ? (unsigned long long)q : 0ull;
+    if (!(q < 18446744073709551616.0)) v = lim;
+    c[k] = v > lim ? lim : v;
+  }
+  uint64_t key = 0;
+  for (int b = maxb - 1; b >= 0; --b) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (b < bits[k]) key = (key << 1) | ((c[k] >> b) & 1ull);
+    }
+  }
+  return key;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_keys(Work W) {
+  __shared__ uint32_t s_hist[8][256];
+  for (int i = threadIdx.x; i < 8 * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  const GridDesc* g = W.desc;
+  int bits[D];
+  int maxb = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    bits[k] = g->bits[k];
+    maxb = max(maxb, bits[k]);
+  }
+  const int passes = g->passes;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = W.pts[(size_t)i * D + k];
+    const uint64_t key = morton_key<D>(x, g, bits, maxb);
+    W.keyA[i] = key;
+    W.idxA[i] = (uint32_t)i;
+    for (int p = 0; p < passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * 256; i += kBlock) {
+    const uint32_t v = (&s_hist[0][0])[i];
+    if (v) atomicAdd(&W.ghist[i], v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One 8-bit LSD radix pass (stable), single kernel per pass: tiles are taken in
+// order from an atomic counter, ranked inside the tile with wave ballots, and
+// offset across tiles with decoupled look-back per digit.
+// ---------------------------------------------------------------------------
+DB_DEV uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_tmp /*[kWavesPerBlock]*/) {
+  const int w = threadIdx.x / kWave;
+  const int incl = wave_incl_scan((int)v);
+  if (lane_id() == kWave - 1) s_tmp[w] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int j = 0; j < w; ++j) off += s_tmp[j];
+  __syncthreads();
+  return off + (uint32_t)incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_pass(Work W, int pass, int ntiles) {
+  __shared__ uint32_t s_wcnt[kWavesPerBlock][256];
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_tmp[kWavesPerBlock];
+  __shared__ int s_tile;
+  const GridDesc* g = W.desc;
+  if (pass >= g->passes) return;
+  const uint64_t* kin = (pass & 1) ? W.keyB : W.keyA;
+  const uint32_t* vin = (pass & 1) ? W.idxB : W.idxA;
+  uint64_t* kout = (pass & 1) ? W.keyA : W.keyB;
+  uint32_t* vout = (pass & 1) ? W.idxA : W.idxB;
+  const uint32_t epoch = epoch_of(g, pass);
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  if (tid == 0) s_tile = atomicAdd(&W.tilectr[pass], 1);
+  for (int i = tid; i < kWavesPerBlock * 256; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const int tile = s_tile;
+  const int shift = 8 * pass;
+  const int n = W.n;
+
+  uint64_t key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t rnk[kSortItems];
+  const int base_idx = tile * kTile + w * (kWave * kSortItems);
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int idx = base_idx + j * kWave + lane;
+    const bool valid = idx < n;
+    key[j] = valid ? kin[idx] : 0ull;
+    val[j] = valid ? vin[idx] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int idx = base_idx + j * kWave + lane;
+    const bool valid = idx < n;
+    const uint32_t digit = (uint32_t)(key[j] >> shift) & 255u;
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (digit >> b) & 1u;
+      const uint64_t bb = ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const uint32_t old = valid ? s_wcnt[w][digit] : 0u;
+    wave_sync();
+    if (valid && before == 0) s_wcnt[w][digit] = old + cnt;
+    wave_sync();
+    rnk[j] = old + before;
+  }
+  __syncthreads();
+  // per digit: offsets of each wave inside the tile, tile total, look-back.
+  {
+    const int dg = tid;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+      const uint32_t t = s_wcnt[w2][dg];
+      s_wcnt[w2][dg] = run;
+      run += t;
+    }
+    uint64_t* st = W.lbstate + (size_t)tile * 256 + dg;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      st_rel(st, lb_word(epoch, kFlagIncl, run));
+    } else {
+      st_rel(st, lb_word(epoch, kFlagAgg, run));
+      excl = lookback_exclusive(W.lbstate + dg, 256, tile, epoch, &W.desc->status);
+      st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
+    }
+    const uint32_t gstart = block_excl_scan_256(W.ghist[pass * 256 + dg], s_tmp);
+    s_base[dg] = gstart + excl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int idx = base_idx + j * kWave + lane;
+    if (idx < n) {
+      const uint32_t digit = (uint32_t)(key[j] >> shift) & 255u;
+      const uint32_t dst = s_base[digit] + s_wcnt[w][digit] + rnk[j];
+      if (dst < (uint32_t)n) {  // always true unless a look-back wait expired
+        kout[dst] = key[j];
+        vout[dst] = val[j];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2/a3: cell runs.  mode 0: a new cell starts where the sorted key changes, and
+// the points are gathered into cell order (SoA).  mode 1 (only when some cell
+// failed the diameter guard): additionally every point of an unsafe cell becomes
+// a cell of its own, written to the second set of cell arrays.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
+  __shared__ uint32_t s_tmp[kWavesPerBlock];
+  __shared__ uint32_t s_excl;
+  __shared__ uint32_t s_tot;
+  __shared__ int s_tile;
+  const GridDesc* g = W.desc;
+  if (mode == 1 && g->n_unsafe == 0) return;
+  const int n = W.n;
+  const bool odd = (g->passes & 1) != 0;
+  const uint64_t* keys = odd ? W.keyB : W.keyA;
+  const uint32_t* idx = odd ? W.idxB : W.idxA;
+  int32_t* cof = mode ? W.cellOf2 : W.cellOf;
+  int32_t* cst = mode ? W.cellStart2 : W.cellStart;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_tile = atomicAdd(&W.tilectr[8 + mode], 1);
+  __syncthreads();
+  const int tile = s_tile;
+  const uint32_t epoch = epoch_of(g, 8 + mode);
+
+  bool head[kSortItems];
+  uint32_t pre[kSortItems];
+  uint32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int i = tile * kTile + j * kBlock + tid;
+    bool h = false;
+    if (i < n) {
+      if (i == 0) {
+        h = true;
+      } else if (mode == 0) {
+        h = keys[i] != keys[i - 1];
+      } else {
+        const int c = W.cellOf[i];
+        h = c != W.cellOf[i - 1] || W.unsafe[c];
+      }
+    }
+    head[j] = h;
+    const uint32_t ex = block_excl_scan_256(h ? 1u : 0u, s_tmp);
+    pre[j] = run + ex;
+    // block total for this j: last thread's exclusive + its flag
+    if (tid == kBlock - 1) s_tot = ex + (h ? 1u : 0u);
+    __syncthreads();
+    run += s_tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    uint64_t* st = W.lbstate + (size_t)tile * 256;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      st_rel(st, lb_word(epoch, kFlagIncl, run));
+    } else {
+      st_rel(st, lb_word(epoch, kFlagAgg, run));
+      excl = lookback_exclusive(W.lbstate, 256, tile, epoch, &W.desc->status);
+      st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
+    }
+    s_excl = excl;
+  }
+  __syncthreads();
+  const uint32_t texcl = s_excl;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int i = tile * kTile + j * kBlock + tid;
+    if (i >= n) continue;
+    int cid = (int)(texcl + pre[j] + (head[j] ? 1u : 0u)) - 1;
+    cid = cid < 0 ? 0 : (cid >= n ? n - 1 : cid);  // clamps only after an expired wait
+    cof[i] = cid;
+    if (head[j]) cst[cid] = i;
+    if (i == n - 1) {
+      cst[cid + 1] = n;
+      W.desc->n_cells = cid + 1;
+    }
+    if (mode == 0) {
+      uint32_t src = idx[i];
+      if (src >= (uint32_t)n) src = 0;  // only after an expired wait
+      W.perm[i] = (int32_t)src;
+#pragma unroll
+      for (int k = 0; k < D; ++k) W.X[(size_t)k * n + i] = W.pts[(size_t)src * D + k];
+    }
+  }
+}
+
+// After a split: the second set of cell arrays becomes the first.
+__global__ void k_cells_copy(Work W) {
+  const GridDesc* g = W.desc;
+  if (g->n_unsafe == 0) return;
+  const int n = W.n, C = g->n_cells;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+    if (i < n) W.cellOf[i] = W.cellOf2[i];
+    if (i <= C) W.cellStart[i] = W.cellStart2[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell float64 point boxes.  Cells fully inside a 64-point chunk are reduced
+// by a segmented wave scan and stored; cells crossing a chunk edge are combined
+// with atomics into boxes initialised to +inf / -inf.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_cell_box_init(Work W, int only_if_split) {
+  const GridDesc* g = W.desc;
+  if (only_if_split && g->n_unsafe == 0) return;
+  const int C = g->n_cells, n = W.n;
+  double* lo = const_cast<double*>(W.tree.lo[0]);
+  double* hi = const_cast<double*>(W.tree.hi[0]);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lo[(size_t)k * n + c] = __builtin_inf();
+      hi[(size_t)k * n + c] = -__builtin_inf();
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) {
+  const GridDesc* g = W.desc;
+  if (only_if_split && g->n_unsafe == 0) return;
+  const int n = W.n;
+  double* lo = const_cast<double*>(W.tree.lo[0]);
+  double* hi = const_cast<double*>(W.tree.hi[0]);
+  const int lane = lane_id();
+  const int nchunks = (n + kWave - 1) / kWave;
+  for (int ch = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; ch < nchunks;
+       ch += gridDim.x * kWavesPerBlock) {
+    const int base = ch * kWave;
+    const int i = base + lane;
+    const bool valid = i < n;
+    const int c = valid ? W.cellOf[i] : -1;
+    const int cn = (i + 1 < n && lane < kWave - 1) ? W.cellOf[i + 1] : -2;
+    const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
+    bool owned = false;
+    if (last) owned = W.cellStart[c] >= base && W.cellStart[c + 1] <= base + kWave;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double a = valid ? W.X[(size_t)k * n + i] : 0.0;
+      double b = a;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const double ua = __shfl_up(a, o, kWave);
+        const double ub = __shfl_up(b, o, kWave);
+        const int uc = __shfl_up(c, o, kWave);
+        if (lane >= o && uc == c) {
+          a = fmin(a, ua);
+          b = fmax(b, ub);
+        }
+      }
+      if (last) {
+        if (owned) {
+          lo[(size_t)k * n + c] = a;
+          hi[(size_t)k * n + c] = b;
+        } else {
+          atomic_min_double(&lo[(size_t)k * n + c], a);
+          atomic_max_double(&hi[(size_t)k * n + c], b);
+        }
+      }
+    }
+  }
+}
+
+// Diameter guard: D(lo, hi) <= E2 proves every pair in the cell is within eps
+// (monotone rounding; see box_sqdist).  The paper's claim that all points of a
+// cell are within eps holds in exact arithmetic only.
+template <int D>
+__global__ void k_cell_safe(Work W) {
+  GridDesc* g = W.desc;
+  const int C = g->n_cells, n = W.n;
+  int bad = 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+    double a[D], b[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      a[k] = W.tree.lo[0][(size_t)k * n + c];
+      b[k] = W.tree.hi[0][(size_t)k * n + c];
+    }
+    const bool uns = !(sqdist<D>(a, b) <= W.E2);
+    W.unsafe[c] = uns;
+    bad += uns;
+  }
+  bad = wave_sum(bad);
+  if (lane_id() == 0 && bad) atomicAdd(&g->n_unsafe, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Tree level l: node j bounds children [64 j, 64 j + 64) of level l - 1.
+// ---------------------------------------------------------------------------
+DB_DEV int level_count(int C, int l) {
+  long long c = C;
+  for (int i = 0; i < l; ++i) c = (c + 63) >> 6;
+  return (int)c;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_tree_level(Work W, int l) {
+  const int C = W.desc->n_cells;
+  const int nchild = level_count(C, l - 1);
+  const int nnode = (nchild + 63) >> 6;
+  const double* clo = W.tree.lo[l - 1];
+  const double* chi = W.tree.hi[l - 1];
+  const int cs = W.tree.cap[l - 1];
+  double* plo = const_cast<double*>(W.tree.lo[l]);
+  double* phi = const_cast<double*>(W.tree.hi[l]);
+  const int ps = W.tree.cap[l];
+  const int lane = lane_id();
+  for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < nnode;
+       j += gridDim.x * kWavesPerBlock) {
+    const int ch = j * 64 + lane;
+    const bool v = ch < nchild;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
+      const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
+      if (lane == 0) {
+        plo[(size_t)k * ps + j] = a;
+        phi[(size_t)k * ps + j] = b;
+      }
+    }
+  }
+}
+
+}  // namespace db

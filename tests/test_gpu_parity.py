@@ -1,0 +1,188 @@
+"""HIP path against the CPU oracle: element-by-element parity, edge cases, errors.
+
+Expected values come only from the oracle (O1, pinned to the brute-force O0) or
+from the fixtures under golden/; nothing expected is produced by the HIP path.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dbscan_brute, dbscan_o1
+from tests.gpu_helpers import digest, full_size_cases, gpu_dbscan, log
+from tests.pins import ALL_PINS
+from workloads import blobs_2d, config_workload, gaussian_mixture, multi_cloud_batch, seed_spreader_3d
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64"]
+
+
+def _impl(mode):
+    def f(X, eps, mp):
+        return gpu_dbscan(X, eps, mp, mode=mode, tag="pin")
+
+    return f
+
+
+def _assert_parity(X, eps, mp, mode, tag, oracle=dbscan_o1):
+    want = oracle(X, eps, mp)
+    got = gpu_dbscan(X, eps, mp, mode=mode, tag=tag)
+    bad_core = np.flatnonzero(got[0] != want[0])
+    bad_lab = np.flatnonzero(got[1] != want[1])
+    assert bad_core.size == 0, f"{tag}: {bad_core.size} core flags differ, first {bad_core[:5]}"
+    assert bad_lab.size == 0, (
+        f"{tag}: {bad_lab.size} labels differ, first idx {bad_lab[:5]} "
+        f"got {got[1][bad_lab[:5]]} want {want[1][bad_lab[:5]]}"
+    )
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("pin", sorted(ALL_PINS))
+def test_pins_on_gpu(pin, mode, gpu_lib):
+    fails = ALL_PINS[pin](_impl(mode))
+    assert not fails, "\n".join(fails)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mp", [1, 4, 10, 30, 100])
+def test_blobs(mp, mode, gpu_lib):
+    _assert_parity(blobs_2d(6000, seed=201), 100.0, mp, mode, f"blobs mp={mp}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("eps,mp", [(200.0, 10), (400.0, 50), (120.0, 5), (60.0, 100)])
+def test_seed_spreader(eps, mp, mode, gpu_lib):
+    n = 60_000
+    X = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=202)
+    _assert_parity(X, eps, mp, mode, f"spreader eps={eps} mp={mp}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [4, 5, 7, 8])
+@pytest.mark.parametrize("eps", [1.5, 3.0])
+def test_high_dim(d, eps, mode, gpu_lib):
+    rng = np.random.Generator(np.random.PCG64(203 + d))
+    X = gaussian_mixture(8000, d, 12, 1.0, 16.0, 0.05, rng)
+    _assert_parity(X, eps, 10, mode, f"mixture d={d} eps={eps}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_multi_cloud_small(mode, gpu_lib):
+    for i, inst in enumerate(multi_cloud_batch(n_clouds=16, size_scale=0.01)):
+        _assert_parity(inst.X, inst.eps[0], inst.min_pts[0], mode, f"cloud {i} d={inst.d}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_lattice_exact_boundaries(d, mode, gpu_lib):
+    rng = np.random.Generator(np.random.PCG64(204))
+    P = rng.integers(0, 12, size=(5000, d)).astype(np.float64)
+    for mp in (2, 3, 2 * d + 1, 40):
+        _assert_parity(P, 1.0, mp, mode, f"lattice d={d} mp={mp}")
+
+
+# eps values for which a grid cell of side fl(eps / fl(sqrt(d))) contains two
+# corner points whose float64 distance test fails (found by search): the dense-cell
+# shortcut would be wrong there without the diameter guard.
+UNSAFE_EPS = [(3, 2.464117292042362), (7, 2.379220351910591)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d,eps", UNSAFE_EPS)
+def test_unsafe_cells_split(d, eps, mode, gpu_lib):
+    s = eps / np.sqrt(d)
+    hi = np.nextafter(s, 0.0)
+    lo_pts = np.zeros((6, d))
+    hi_pts = np.full((6, d), hi)
+    rng = np.random.Generator(np.random.PCG64(205))
+    far = rng.uniform(5 * eps, 9 * eps, size=(300, d))
+    X = np.concatenate([lo_pts, hi_pts, far])
+    (got, st) = gpu_dbscan(X, eps, 10, mode=mode, tag=f"unsafe d={d}", want_stats=True)
+    want = dbscan_o1(X, eps, 10)
+    assert st["n_unsafe"] >= 1, st
+    assert not want[0][:12].any(), "test data must make the corner points non-core"
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases(mode, gpu_lib):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    log("edge n=0")
+    core, lab = binding.dbscan(torch.zeros((0, 3), dtype=torch.float64, device="cuda"), 1.0, 5, mode=mode)
+    assert core.numel() == 0 and lab.numel() == 0
+    _assert_parity(np.array([[1.0, 2.0]]), 0.5, 1, mode, "single point mp=1")
+    _assert_parity(np.array([[1.0, 2.0]]), 0.5, 2, mode, "single point mp=2")
+    _assert_parity(np.full((3000, 2), 7.5), 0.1, 10, mode, "all duplicates")
+    rng = np.random.Generator(np.random.PCG64(206))
+    X = rng.uniform(0, 10, size=(4000, 3))
+    _assert_parity(X, 0.7, 4001, mode, "minPts > n")
+    _assert_parity(X, 0.7, 1, mode, "minPts = 1")
+    _assert_parity(X, 100.0, 50, mode, "eps above diameter")
+    _assert_parity(X, 1e-6, 2, mode, "tiny eps", oracle=dbscan_brute)
+    # sparse cells with more than 64 points: minPts far above the per-cell count
+    Y = rng.uniform(0, 4, size=(20000, 2))
+    _assert_parity(Y, 0.3, 300, mode, "minPts 300")
+    _assert_parity(rng.uniform(0, 100, size=(7000, 1)), 0.05, 3, mode, "d=1")
+    _assert_parity(rng.normal(0, 1, size=(5000, 8)), 2.0, 6, mode, "d=8")
+    # ragged sizes around tile edges (radix tiles of 2048 points, waves of 64)
+    for n in (63, 64, 65, 2047, 2048, 2049, 4097):
+        Z = rng.uniform(0, 30, size=(n, 2))
+        _assert_parity(Z, 1.0, 3, mode, f"ragged n={n}")
+
+
+def test_device_errors(gpu_lib):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    X = torch.zeros((100, 2), dtype=torch.float64, device="cuda")
+    X[7, 1] = float("nan")
+    log("error nonfinite")
+    with pytest.raises(binding.DbscanError) as e:
+        binding.dbscan(X, 1.0, 3)
+    assert e.value.code == binding.ENONFINITE
+    # extreme extent: the key is coarsened and the result still matches the oracle
+    for mp in (1, 2):
+        Y = np.array([[0.0, 0.0], [1e300, 1e300], [1e300, 1e300 + 1e284]])
+        (got, st) = gpu_dbscan(Y, 1.0, mp, tag=f"extreme extent mp={mp}", want_stats=True)
+        want = dbscan_brute(Y, 1.0, mp)
+        assert st["key_shift"] > 0, st
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    Z = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+    for eps, mp in ((0.0, 3), (-1.0, 3), (float("inf"), 3), (float("nan"), 3), (1.0, 0)):
+        with pytest.raises(binding.DbscanError) as e:
+            binding.dbscan(Z, eps, mp)
+        assert e.value.code == binding.EINVAL
+    with pytest.raises(binding.DbscanError) as e:
+        binding.dbscan(torch.zeros((10, 9), dtype=torch.float64, device="cuda"), 1.0, 2)
+    assert e.value.code == binding.EINVAL
+    # the context still works after errors
+    _assert_parity(np.random.default_rng(1).uniform(0, 5, (500, 2)), 0.4, 4, "fp64", "after errors")
+
+
+def test_determinism(gpu_lib):
+    n = 100_000
+    X = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=207)
+    ref = gpu_dbscan(X, 150.0, 10, tag="determinism 0")
+    for r in range(1, 6):
+        got = gpu_dbscan(X, 150.0, 10, tag=f"determinism {r}")
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("name", sorted(full_size_cases()))
+def test_full_size_against_oracle_hash(name, mode, gpu_lib):
+    case = full_size_cases()[name]
+    X = config_workload(case["config"], case["scale"])[0].X
+    assert len(X) == case["n"]
+    core, lab = gpu_dbscan(X, case["eps"], case["min_pts"], mode=mode, tag=name)
+    summary = {
+        "n_core": int(core.sum()),
+        "n_noise": int((lab < 0).sum()),
+        "n_clusters": int(len(np.unique(lab[core.astype(bool)]))),
+    }
+    assert summary == {k: case[k] for k in summary}, (summary, case)
+    assert digest(core, lab) == case["sha256"]
