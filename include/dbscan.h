@@ -117,15 +117,35 @@ int dbscan_get_stats(dbscan_ctx *ctx, void *stream, dbscan_stats *out);
 /*
  * Phase timing.  With profiling on, each call records HIP events on its stream
  * between its phases (grid box, keys, radix sort, cell runs, cell boxes and
- * guard, box tree, MarkCore, core counts, ClusterCore, relabel, ClusterBorder,
- * output scatter).  dbscan_phase_times() synchronises `stream` and writes up to
+ * guard, box tree, MarkCore, ClusterCore, relabel, ClusterBorder, output
+ * scatter).  dbscan_phase_times() synchronises `stream` and writes up to
  * `cap` per-phase durations in milliseconds of the last call; it returns the
  * number of phases (DBSCAN_NUM_PHASES) or a negative error code.
  */
-#define DBSCAN_NUM_PHASES 12
+#define DBSCAN_NUM_PHASES 11
 int dbscan_set_profiling(dbscan_ctx *ctx, int on);
 int dbscan_phase_times(dbscan_ctx *ctx, void *stream, float *ms, int32_t cap);
 const char *dbscan_phase_name(int32_t phase);
+
+/*
+ * Tuning options of a context (they change speed, never results).
+ *   DBSCAN_OPT_BCP_ROUNDS  0: one pass tests every neighbour cell pair;
+ *                          1: rounds over the levels of the cell tree, each
+ *                             pruning subtrees already joined;
+ *                          -1: automatic (one pass for d <= 3, rounds above;
+ *                             the default)
+ *   DBSCAN_OPT_UNIT_LEVEL  in rounds, tree nodes up to this level whose core
+ *                          cells already form one component are tested as one
+ *                          unit (0..5, default 1)
+ *   DBSCAN_OPT_FINE_BITS   sub-cell Morton bits per dimension used to order the
+ *                          points inside a cell (-1: automatic = 0, else 0..8)
+ * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
+ */
+#define DBSCAN_OPT_BCP_ROUNDS 1
+#define DBSCAN_OPT_UNIT_LEVEL 2
+#define DBSCAN_OPT_FINE_BITS 3
+int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
+int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 
 /* Static description of a return code. */
 const char *dbscan_strerror(int code);

@@ -13,7 +13,7 @@ import re
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdbscan_hip.so")
+LIB_PATH = os.environ.get("DBSCAN_HIP_LIB") or os.path.join(HERE, "libdbscan_hip.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "dbscan.h")
 
 OK = 0
@@ -22,6 +22,8 @@ ENOMEM = -2
 EHIP = -3
 ENONFINITE = -4
 EINTERNAL = -5
+
+OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1
@@ -74,6 +76,8 @@ def load():
     lib.dbscan_reserve.argtypes = [vp, i64, i32]
     lib.dbscan.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp]
     lib.dbscan_get_stats.argtypes = [vp, vp, ctypes.POINTER(Stats)]
+    lib.dbscan_set_option.argtypes = [vp, i32, i64]
+    lib.dbscan_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.dbscan_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.dbscan_phase_times.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.dbscan_phase_name.argtypes = [i32]
@@ -81,7 +85,7 @@ def load():
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
-              "dbscan_set_profiling", "dbscan_phase_times"):
+              "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -184,3 +188,13 @@ def phase_times(device: int = 0, stream=None) -> dict:
     if k < 0:
         raise DbscanError(k, "dbscan_phase_times")
     return {lib.dbscan_phase_name(i).decode(): float(buf[i]) for i in range(k)}
+
+
+def set_option(name: str, value: int, device: int = 0) -> None:
+    _check(load().dbscan_set_option(context(device), OPTIONS[name], int(value)), f"set_option {name}")
+
+
+def get_option(name: str, device: int = 0) -> int:
+    v = ctypes.c_int64()
+    _check(load().dbscan_get_option(context(device), OPTIONS[name], ctypes.byref(v)), f"get_option {name}")
+    return int(v.value)

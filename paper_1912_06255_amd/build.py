@@ -35,9 +35,10 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, SRC]
+def build(verbose: bool = False, out: str | None = None, defines: tuple = ()) -> str:
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-o", tmp, SRC]
     t0 = time.time()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -48,9 +49,9 @@ def build(verbose: bool = False) -> str:
         for line in (res.stdout + res.stderr).splitlines():
             if noise not in line:
                 sys.stderr.write(line + "\n")
-        print(f"built {LIB} in {time.time() - t0:.1f}s")
-    os.replace(tmp, LIB)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f}s")
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

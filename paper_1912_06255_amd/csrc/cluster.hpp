@@ -9,6 +9,7 @@
 namespace db {
 
 constexpr int kIntMax = 0x7fffffff;
+constexpr int kNodeNoCore = -2;
 
 // ---------------------------------------------------------------------------
 // Tree walk.  Every node whose box can hold a point within eps of the query box
@@ -23,39 +24,81 @@ struct Query {
   double E2;
 };
 
+// Visitors provide:
+//   static constexpr bool kNearestFirst  enter child nodes by increasing box distance
+//   bool keep_node(int level, int idx)   false drops a node (level >= 1) unvisited
+//   bool group(int first_cell, uint64_t mask)
 template <int D, int L, class V>
 DB_DEV bool visit_node(const TreeView& T, const int (&cnt)[kTreeLevels + 2], int node,
                        const Query<D>& q, V& vis) {
   const int cb = node * 64;
   const int ch = cb + lane_id();
-  bool ok = false;
-  if (ch < cnt[L - 1]) ok = box_sqdist<D>(q.lo, q.hi, T.lo[L - 1], T.hi[L - 1], T.cap[L - 1], ch) <= q.E2;
+  double dist = __builtin_inf();
+  if (ch < cnt[L - 1]) {
+    const double bd = box_sqdist<D>(q.lo, q.hi, T.lo[L - 1], T.hi[L - 1], T.cap[L - 1], ch);
+    if (bd <= q.E2) dist = bd;
+  }
+  bool ok = dist <= q.E2;
+  if constexpr (L >= 2) {
+    if (ok) ok = vis.keep_node(L - 1, ch);
+  }
   uint64_t m = ballot(ok);
   if constexpr (L == 1) {
     return m ? vis.group(cb, m) : false;
   } else {
-    while (m) {
-      const int j = __ffsll((long long)m) - 1;
-      m &= m - 1;
-      if (visit_node<D, L - 1, V>(T, cnt, cb + j, q, vis)) return true;
+    if constexpr (V::kNearestFirst) {
+      if (!ok) dist = __builtin_inf();
+      while (m) {
+        const double mind = wave_min(dist);
+        const int j = __ffsll((long long)(ballot(dist == mind) & m)) - 1;
+        m &= ~(1ull << j);
+        if (lane_id() == j) dist = __builtin_inf();
+        if (visit_node<D, L - 1, V>(T, cnt, cb + j, q, vis)) return true;
+      }
+    } else {
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        if (visit_node<D, L - 1, V>(T, cnt, cb + j, q, vis)) return true;
+      }
     }
     return false;
+  }
+}
+
+DB_DEV void level_counts(int C, int (&cnt)[kTreeLevels + 2]) {
+  cnt[0] = C;
+#pragma unroll
+  for (int l = 1; l < kTreeLevels + 2; ++l) cnt[l] = (cnt[l - 1] + 63) >> 6;
+}
+
+// Top node level: the first with at most 64 nodes.  The whole tree is the subtree
+// of a virtual node (index 0) one level above it.
+DB_DEV int top_level(const int (&cnt)[kTreeLevels + 2]) {
+  int top = 1;
+  while (top < kTreeLevels && cnt[top] > 64) ++top;
+  return top;
+}
+
+// Walk the subtree of node `node` at level `level` (1 .. top + 1).
+template <int D, class V>
+DB_DEV void walk_subtree(const TreeView& T, const int (&cnt)[kTreeLevels + 2], int level, int node,
+                         const Query<D>& q, V& vis) {
+  switch (level) {
+    case 1: visit_node<D, 1, V>(T, cnt, node, q, vis); break;
+    case 2: visit_node<D, 2, V>(T, cnt, node, q, vis); break;
+    case 3: visit_node<D, 3, V>(T, cnt, node, q, vis); break;
+    case 4: visit_node<D, 4, V>(T, cnt, node, q, vis); break;
+    case 5: visit_node<D, 5, V>(T, cnt, node, q, vis); break;
+    default: visit_node<D, 6, V>(T, cnt, node, q, vis); break;
   }
 }
 
 template <int D, class V>
 DB_DEV void walk(const TreeView& T, int C, const Query<D>& q, V& vis) {
   int cnt[kTreeLevels + 2];
-  cnt[0] = C;
-#pragma unroll
-  for (int l = 1; l < kTreeLevels + 2; ++l) cnt[l] = (cnt[l - 1] + 63) >> 6;
-  // top = first node level with at most 64 nodes; the walk starts at a virtual
-  // parent one level above whose only child group is that level.
-  if (cnt[1] <= 64) visit_node<D, 2, V>(T, cnt, 0, q, vis);
-  else if (cnt[2] <= 64) visit_node<D, 3, V>(T, cnt, 0, q, vis);
-  else if (cnt[3] <= 64) visit_node<D, 4, V>(T, cnt, 0, q, vis);
-  else if (cnt[4] <= 64) visit_node<D, 5, V>(T, cnt, 0, q, vis);
-  else visit_node<D, 6, V>(T, cnt, 0, q, vis);
+  level_counts(C, cnt);
+  walk_subtree<D, V>(T, cnt, top_level(cnt) + 1, 0, q, vis);
 }
 
 // The tree has kTreeLevels node levels; visit_node<.., 6> reads level 5 boxes.
@@ -119,11 +162,22 @@ DB_DEV void load_box(const TreeView& T, int c, Query<D>& q) {
 // the smaller with a CAS on the root, and path halving only ever stores an
 // ancestor, so racing finds and links stay consistent.
 // ---------------------------------------------------------------------------
+#ifndef DB_UF_COHERENT
+#define DB_UF_COHERENT 1
+#endif
+DB_DEV int uf_load(const int32_t* p) {
+#if DB_UF_COHERENT
+  return ld_acq(p);
+#else
+  return *(volatile const int32_t*)p;
+#endif
+}
+
 DB_DEV int uf_find(int32_t* parent, int x) {
   while (true) {
-    const int p = ld_acq(&parent[x]);
+    const int p = uf_load(&parent[x]);
     if (p == x) return x;
-    const int gp = ld_acq(&parent[p]);
+    const int gp = uf_load(&parent[p]);
     if (gp != p) st_rel(&parent[x], gp);
     x = gp;
   }
@@ -141,6 +195,7 @@ DB_DEV bool uf_link(int32_t* parent, int a, int b) {
     }
     const int old = atomicCAS(&parent[a], a, b);
     if (old == a) return true;
+    a = old;  // a was linked meanwhile: continue from its new parent
   }
 }
 
@@ -153,6 +208,8 @@ DB_DEV bool uf_link(int32_t* parent, int a, int b) {
 // ---------------------------------------------------------------------------
 template <int D>
 struct MarkCoreVisitor {
+  static constexpr bool kNearestFirst = true;
+  DB_DEV bool keep_node(int, int) const { return true; }
   const Work* W;
   Flat F;
   int g, ps, pm;
@@ -184,11 +241,11 @@ struct MarkCoreVisitor {
         pend &= pend - 1;
         double xp[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) xp[d] = __shfl(p[d], t, kWave);
+        for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
         const bool hit = valid && sqdist<D>(xp, xq) <= W->E2;
         const int add = __popcll(ballot(hit));
         if (lane == t) cnt += add;
-        const int ct = __shfl(cnt, t, kWave);
+        const int ct = bcast(cnt, t);
         if (ct >= W->minPts) pending &= ~(1ull << t);
       }
       if (!pending) return true;
@@ -197,6 +254,8 @@ struct MarkCoreVisitor {
   }
 };
 
+// Besides the core flags, each cell's wave records its number of core points and
+// the smallest input index among them, and initialises the union-find entry.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
@@ -204,125 +263,174 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
+  int ncore = 0;
   for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
     const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
+    int cc = 0, mn = kIntMax;
     if (m >= W.minPts) {
-      for (int i = s + lane; i < e; i += kWave) W.coreS[i] = 1;
-      continue;
-    }
-    Query<D> q;
-    q.E2 = W.E2;
-    load_box<D>(W.tree, g, q);
-    for (int ps = s; ps < e; ps += kWave) {
-      MarkCoreVisitor<D> v;
-      v.W = &W;
-      v.F = Flat{s_pref[w], s_start[w]};
-      v.g = g;
-      v.ps = ps;
-      v.pm = min(kWave, e - ps);
-      v.cnt = m;
-      v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
-      if (lane < v.pm) load_point<D>(W.X, n, ps + lane, v.p);
-      else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) v.p[d] = 0.0;
+      for (int i = s + lane; i < e; i += kWave) {
+        W.coreS[i] = 1;
+        mn = min(mn, W.perm[i]);
       }
-      walk<D>(W.tree, C, q, v);
-      if (lane < v.pm) W.coreS[ps + lane] = v.cnt >= W.minPts ? 1 : 0;
+      cc = m;
+    } else {
+      Query<D> q;
+      q.E2 = W.E2;
+      load_box<D>(W.tree, g, q);
+      for (int ps = s; ps < e; ps += kWave) {
+        MarkCoreVisitor<D> v;
+        v.W = &W;
+        v.F = Flat{s_pref[w], s_start[w]};
+        v.g = g;
+        v.ps = ps;
+        v.pm = min(kWave, e - ps);
+        v.cnt = m;
+        v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
+        if (lane < v.pm) load_point<D>(W.X, n, ps + lane, v.p);
+        else {
+#pragma unroll
+          for (int d = 0; d < D; ++d) v.p[d] = 0.0;
+        }
+        walk<D>(W.tree, C, q, v);
+        const bool core = lane < v.pm && v.cnt >= W.minPts;
+        if (lane < v.pm) W.coreS[ps + lane] = core ? 1 : 0;
+        if (core) mn = min(mn, W.perm[ps + lane]);
+        cc += __popcll(ballot(core));
+      }
     }
-  }
-}
-
-// Core points per cell, union-find and relabel initialisation.
-__global__ void k_core_count(Work W) {
-  const int C = W.desc->n_cells;
-  int ncore = 0;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-    const int s = W.cellStart[c], e = W.cellStart[c + 1];
-    int cc = e - s;
-    if (cc < W.minPts) {
-      cc = 0;
-      for (int i = s; i < e; ++i) cc += W.coreS[i];
+    mn = wave_min(mn);
+    if (lane == 0) {
+      W.coreCount[g] = cc;
+      W.cellMin[g] = mn;
+      W.parent[g] = g;
+      W.minIdx[g] = kIntMax;
     }
-    W.coreCount[c] = cc;
-    W.parent[c] = c;
-    W.minIdx[c] = kIntMax;
     ncore += cc;
   }
-  ncore = wave_sum(ncore);
-  if (lane_id() == 0 && ncore) atomicAdd(&W.desc->n_core, ncore);
+  if (lane == 0 && ncore) atomicAdd(&W.desc->n_core, ncore);
 }
 
 // ---------------------------------------------------------------------------
-// ClusterCore (Algorithm 3).  For core cell g and each core neighbour h with
-// h < g whose union-find root differs from g's, test pairs of core points of g
-// and h (BCP with early exit: the first pair within eps links the cells).  Points
-// of g are first filtered by their box distance to the live neighbour cells
-// (the paper's filter of points farther than eps from the other cell).
+// ClusterCore (Algorithm 3).  A unit (a core cell, or a tree node whose core
+// cells already form one component) is tested against each core neighbour cell h
+// of lower index whose union-find root differs: pairs of core points are scanned
+// until the first pair within eps, which links the two (BCP with early exit).
+// Points farther than eps from the other side's box drop out first (the paper's
+// filter), and 64 x 64 tiles whose chunk boxes are farther than eps apart are
+// skipped whole.
 // ---------------------------------------------------------------------------
 template <int D>
 struct BcpVisitor {
+  static constexpr bool kNearestFirst = false;
   const Work* W;
   Flat F;
-  int g, gs, ge;
-  bool gdense;
+  int ps, pe;      // sorted point range of the unit (its core points take part)
+  int hmax;        // candidate cells are those with index < hmax
+  int ucell;       // a core cell of the unit; links are made from it
+  int rg;          // a root of the unit's component (refreshed per group; stale is safe)
+  Query<D> uq;     // box of the unit
+  int excl_level;  // node already covered by an earlier round (level, index), or -1
+  int excl_idx;
+  bool prune;      // node roots of the previous round are valid
+
+  // A node is skipped when an earlier round already handled it, when it has no
+  // core cell, or when all its core cells were in one component that the unit has
+  // joined since (components only merge, so this stays true).
+  DB_DEV bool keep_node(int level, int idx) const {
+    if (level == excl_level && idx == excl_idx) return false;
+    if (!prune) return true;
+    const int r = W->nroot[level][idx];
+    if (r == kNodeNoCore) return false;
+    if (r < 0) return true;
+    return uf_find(W->parent, r) != rg;
+  }
 
   DB_DEV bool group(int cb, uint64_t m) {
     const int lane = lane_id();
     const int n = W->n;
     const int h = cb + lane;
-    bool on = ((m >> lane) & 1ull) && h < g && W->coreCount[h] > 0;
-    const int rg = uf_find(W->parent, g);
-    if (on) on = uf_find(W->parent, h) != rg;
+    bool on = ((m >> lane) & 1ull) && h < hmax && W->coreCount[h] > 0;
+    rg = uf_find(W->parent, ucell);
+    int hr = -1;
+    if (on) {
+      hr = uf_find(W->parent, h);
+      on = hr != rg;
+    }
     uint64_t alive = ballot(on);
     if (!alive) return false;
     if (lane == 0) atomicAdd(&W->desc->bcp_calls, (unsigned long long)__popcll(alive));
-    // union box of the live cells
-    Query<D> ub;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const double a = on ? W->tree.lo[0][(size_t)d * W->tree.cap[0] + h] : __builtin_inf();
-      const double b = on ? W->tree.hi[0][(size_t)d * W->tree.cap[0] + h] : -__builtin_inf();
-      ub.lo[d] = wave_min(a);
-      ub.hi[d] = wave_max(b);
-    }
+    const int c0 = ps >> 6;
+    const int nchk = ((pe - 1) >> 6) - c0 + 1;
     const int tot = flatten(F, W->cellStart, cb, alive);
     for (int base = 0; base < tot && alive; base += kWave) {
       const int k = base + lane;
       bool valid = k < tot;
       int j = 0, q = 0;
       double xq[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) xq[d] = 0.0;
       if (valid) {
         locate(F, k, j, q);
         valid = W->coreS[q] != 0 && ((alive >> j) & 1ull);
       }
-      if (valid) load_point<D>(W->X, n, q, xq);
-      else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) xq[d] = 0.0;
+      if (valid) {
+        load_point<D>(W->X, n, q, xq);
+        // points of h farther than eps from the unit's box drop out
+        valid = box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
       }
       if (!ballot(valid)) continue;
-      for (int p = gs; p < ge; ++p) {
-        if (!gdense && !W->coreS[p]) continue;
-        double xp[D];
-        load_point<D>(W->X, n, p, xp);
-        if (box_sqdist<D>(xp, xp, ub.lo, ub.hi, 1, 0) > W->E2) continue;
-        const bool hit = valid && sqdist<D>(xp, xq) <= W->E2;
-        if (ballot(hit)) {
-          const uint64_t cells = wave_or(hit ? (1ull << j) : 0ull);
-          if (lane == 0) {
-            unsigned long long links = 0;
-            uint64_t cm = cells;
-            while (cm) {
-              const int b = __ffsll((long long)cm) - 1;
-              cm &= cm - 1;
-              links += uf_link(W->parent, g, cb + b) ? 1 : 0;
-            }
-            if (links) atomicAdd(&W->desc->uf_links, links);
+      double qlo[D], qhi[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        qlo[d] = wave_min(valid ? xq[d] : __builtin_inf());
+        qhi[d] = wave_max(valid ? xq[d] : -__builtin_inf());
+      }
+      bool stop = false;
+      // 64 x 64 tiles: unit chunks whose box is farther than eps from this chunk's
+      // box are skipped whole (the lanes test 64 chunk boxes at once)
+      for (int pc0 = 0; pc0 < nchk && !stop; pc0 += kWave) {
+        const int pcl = pc0 + lane;
+        bool sv = false;
+        if (pcl < nchk)
+          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+        uint64_t sm = ballot(sv);
+        while (sm && !stop) {
+          const int b = __ffsll((long long)sm) - 1;
+          sm &= sm - 1;
+          const int i = (c0 + pc0 + b) * kWave + lane;
+          bool pv = i >= ps && i < pe && W->coreS[i] != 0;
+          double xp[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) xp[d] = 0.0;
+          if (pv) {
+            load_point<D>(W->X, n, i, xp);
+            pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
           }
-          alive &= ~cells;
-          valid = valid && ((alive >> j) & 1ull);
-          if (!ballot(valid)) break;
+          uint64_t pm = ballot(pv);
+          while (pm) {
+            const int t = __ffsll((long long)pm) - 1;
+            pm &= pm - 1;
+            double xt[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
+            const bool hit = valid && sqdist<D>(xt, xq) <= W->E2;
+            if (!ballot(hit)) continue;
+            uint64_t cells = wave_or(hit ? (1ull << j) : 0ull);
+            while (cells) {
+              const int c = __ffsll((long long)cells) - 1;
+              cells &= cells - 1;
+              if (!((alive >> c) & 1ull)) continue;
+              const int rc = bcast(hr, c);
+              if (lane == 0 && uf_link(W->parent, ucell, cb + c))
+                atomicAdd(&W->desc->uf_links, 1ull);
+              alive &= ~ballot(hr == rc);  // that whole component has joined
+            }
+            valid = valid && ((alive >> j) & 1ull);
+            if (!ballot(valid)) {
+              stop = true;
+              break;
+            }
+          }
         }
       }
     }
@@ -330,25 +438,91 @@ struct BcpVisitor {
   }
 };
 
+// Round r (0 .. top) connects cells whose lowest common tree ancestor is at level
+// r + 1: each unit walks its level-(r+1) ancestor, leaving out its level-r
+// ancestor handled by earlier rounds (the paper's bucketing: early, local rounds
+// link most cells, so that later rounds skip whole subtrees already in one
+// component).  From round 1 on, a node whose core cells all lie in one component
+// acts as a single unit (its first cell's wave runs it), instead of each of its
+// cells repeating the same links.
+// round = -1: a single pass in which every core cell walks the whole tree.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_bcp(Work W) {
+__global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
   const int C = W.desc->n_cells;
+  int cnt[kTreeLevels + 2];
+  level_counts(C, cnt);
+  const int top = top_level(cnt);
+  if (round > top) return;
   const int w = threadIdx.x / kWave;
   for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
-    if (W.coreCount[g] == 0) continue;
+    const int umax = round < 0 ? 0 : min(round, W.unit_max_level);
+    int ulevel = -1;
+    if (W.coreCount[g] > 0 && (umax == 0 || W.nroot[1][g >> 6] < 0)) ulevel = 0;
+    for (int l = 1; l <= umax && ulevel < 0; ++l) {
+      const int idx = g >> (6 * l);
+      if ((idx << (6 * l)) != g) break;
+      if (W.nroot[l][idx] >= 0 && (l == umax || W.nroot[l + 1][g >> (6 * (l + 1))] < 0)) ulevel = l;
+    }
+    if (ulevel < 0) continue;
     BcpVisitor<D> v;
     v.W = &W;
     v.F = Flat{s_pref[w], s_start[w]};
-    v.g = g;
-    v.gs = W.cellStart[g];
-    v.ge = W.cellStart[g + 1];
-    v.gdense = W.coreCount[g] == v.ge - v.gs;
-    Query<D> q;
-    q.E2 = W.E2;
-    load_box<D>(W.tree, g, q);
-    walk<D>(W.tree, C, q, v);
+    v.uq.E2 = W.E2;
+    if (ulevel == 0) {
+      v.ps = W.cellStart[g];
+      v.pe = W.cellStart[g + 1];
+      v.hmax = g;
+      v.ucell = g;
+      load_box<D>(W.tree, g, v.uq);
+    } else {
+      const int idx = g >> (6 * ulevel);
+      const int first = idx << (6 * ulevel);
+      const int last = min(C, (idx + 1) << (6 * ulevel)) - 1;
+      v.ps = W.cellStart[first];
+      v.pe = W.cellStart[last + 1];
+      v.hmax = first;
+      v.ucell = W.nroot[ulevel][idx];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        v.uq.lo[d] = W.tree.lo[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
+        v.uq.hi[d] = W.tree.hi[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
+      }
+    }
+    v.rg = v.ucell;
+    v.excl_level = round >= 1 ? round : -1;
+    v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
+    v.prune = round >= 1;
+    const int anc_level = round < 0 ? top + 1 : round + 1;
+    const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
+    walk_subtree<D>(W.tree, cnt, anc_level, anc, v.uq, v);
+  }
+}
+
+// Node roots for pruning: per node, the common root of its core cells, -1 when
+// they are in several components, kNodeNoCore when it has no core cell.
+__global__ __launch_bounds__(kBlock) void k_node_roots(Work W, int level) {
+  const int C = W.desc->n_cells;
+  int cnt[kTreeLevels + 2];
+  level_counts(C, cnt);
+  const int lane = lane_id();
+  for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < cnt[level];
+       j += gridDim.x * kWavesPerBlock) {
+    const int ch = j * 64 + lane;
+    int v = kNodeNoCore;
+    if (ch < cnt[level - 1]) {
+      if (level == 1) v = W.coreCount[ch] > 0 ? uf_find(W.parent, ch) : kNodeNoCore;
+      else v = W.nroot[level - 1][ch];
+    }
+    const bool mixed = ballot(v == -1) != 0;
+    const int hi = wave_max(v);
+    const int lo = wave_min(v == kNodeNoCore ? kIntMax : v);
+    int r;
+    if (mixed) r = -1;
+    else if (hi == kNodeNoCore) r = kNodeNoCore;
+    else r = (lo == hi) ? hi : -1;
+    if (lane == 0) W.nroot[level][j] = r;
   }
 }
 
@@ -367,9 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_relabel_min(Work W) {
     int root = -1, mn = kIntMax;
     if (c < C && W.coreCount[c] > 0) {
       root = uf_find(W.parent, c);
-      const int s = W.cellStart[c], e = W.cellStart[c + 1];
-      for (int i = s; i < e; ++i)
-        if (W.coreS[i]) mn = min(mn, W.perm[i]);
+      mn = W.cellMin[c];
     }
     uint64_t todo = ballot(root >= 0);
     while (todo) {
@@ -398,6 +570,8 @@ __global__ void k_cell_label(Work W) {
 // ---------------------------------------------------------------------------
 template <int D>
 struct BorderVisitor {
+  static constexpr bool kNearestFirst = false;
+  DB_DEV bool keep_node(int, int) const { return true; }
   const Work* W;
   Flat F;
   int g, pm;
@@ -434,12 +608,12 @@ struct BorderVisitor {
         for (int d = 0; d < D; ++d) xq[d] = 0.0;
       }
       for (int t = 0; t < pm; ++t) {
-        const int bt = __shfl(best, t, kWave);
+        const int bt = bcast(best, t);
         const bool cand = valid && lq < bt;
         if (!ballot(cand)) continue;
         double xp[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) xp[d] = __shfl(p[d], t, kWave);
+        for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
         const bool hit = cand && sqdist<D>(xp, xq) <= W->E2;
         const int mn = wave_min(hit ? lq : kIntMax);
         if (lane == t && mn < best) best = mn;

@@ -22,6 +22,8 @@ struct GridDesc {
   int32_t bits[kMaxD];    // bits of each cell coordinate in the Morton key
   int32_t total_bits;     // sum of bits
   int32_t shift;          // key coordinate = floor(q / 2^shift), q = cell index
+  int32_t fine_bits;      // sub-cell bits per dimension appended below the cell key
+  int32_t cell_key_shift; // = fine_bits * d: key >> cell_key_shift is the cell key
   int32_t passes;         // 8-bit radix passes needed
   uint32_t epoch;         // bumped once per call; tags look-back words
   uint32_t status;        // DBSCAN_STATUS_* bits
@@ -51,6 +53,18 @@ DB_DEV int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 DB_DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Value of v in lane t (t wave-uniform), through scalar registers.
+DB_DEV double bcast(double v, int t) {
+  const int tt = __builtin_amdgcn_readfirstlane(t);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), tt);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), tt);
+  return __hiloint2double(hi, lo);
+}
+
+DB_DEV int bcast(int v, int t) {
+  return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(t));
 }
 
 DB_DEV int wave_incl_scan(int v) {

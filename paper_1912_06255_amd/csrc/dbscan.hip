@@ -20,6 +20,9 @@ struct dbscan_ctx {
   GridDesc* desc = nullptr;  // lives at the start of scratch, survives growth
   size_t desc_bytes = 0;
   int64_t last_n = 0;
+  int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
+  int unit_level = 1;
+  int fine_bits = -1;   // -1: automatic (0)
   bool profile = false;
   bool events_ready = false;
   bool events_recorded = false;
@@ -61,6 +64,9 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   w.idxA = c.take<uint32_t>(n);
   w.idxB = c.take<uint32_t>(n);
   w.X = c.take<double>(n * d);
+  w.chunkCap = (int)ceil_div(n, 64);
+  w.chunkLo = c.take<double>((int64_t)w.chunkCap * d);
+  w.chunkHi = c.take<double>((int64_t)w.chunkCap * d);
   w.perm = c.take<int32_t>(n);
   w.cellOf = c.take<int32_t>(n);
   w.cellStart = c.take<int32_t>(n + 1);
@@ -73,12 +79,14 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
     w.tree.cap[l] = (int)cap;
     w.tree.lo[l] = c.take<double>(cap * d);
     w.tree.hi[l] = c.take<double>(cap * d);
+    w.nroot[l] = l > 0 ? c.take<int32_t>(cap) : nullptr;
   }
   w.coreS = c.take<uint8_t>(n);
   w.coreCount = c.take<int32_t>(n);
   w.parent = c.take<int32_t>(n);
   w.minIdx = c.take<int32_t>(n);
   w.cellLabel = c.take<int32_t>(n);
+  w.cellMin = c.take<int32_t>(n);
   w.blabel = c.take<int32_t>(n);
   return c.off;
 }
@@ -112,7 +120,7 @@ unsigned grid_for(int64_t items, int per_block, unsigned cap) {
 
 const char* const kPhaseNames[DBSCAN_NUM_PHASES] = {
     "bbox", "keys", "radix_sort", "cells", "cell_boxes", "tree", "markcore",
-    "core_count", "cluster_core", "relabel", "border", "scatter"};
+    "cluster_core", "relabel", "border", "scatter"};
 
 struct Marks {
   hipEvent_t* ev;  // null when profiling is off
@@ -123,7 +131,7 @@ struct Marks {
 };
 
 template <int D>
-int run(const Work& W, hipStream_t s, const Marks& mark) {
+int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
   const int64_t n = W.n;
   const unsigned gp = grid_for(n, kBlock, 2048);           // one thread per point
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);   // one wave per cell
@@ -134,7 +142,7 @@ int run(const Work& W, hipStream_t s, const Marks& mark) {
   mark(0);
   k_init<<<1, kBlock, 0, s>>>(W);
   k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W);
-  k_bbox_final<D><<<1, kWave, 0, s>>>(W, (int)nb);
+  k_bbox_final<D><<<1, kBlock, 0, s>>>(W, (int)nb);
   mark(1);
   k_keys<D><<<gp, kBlock, 0, s>>>(W);
   mark(2);
@@ -158,17 +166,25 @@ int run(const Work& W, hipStream_t s, const Marks& mark) {
   mark(6);
   k_markcore<D><<<gw, kBlock, 0, s>>>(W);
   mark(7);
-  k_core_count<<<gp, kBlock, 0, s>>>(W);
+  if (!rounds) {
+    k_bcp<D><<<gw, kBlock, 0, s>>>(W, -1);
+  } else {
+    for (int round = 0; round < kTreeLevels; ++round) {
+      if (round > 0) {
+        for (int l = 1; l <= kTreeLevels; ++l)
+          k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
+      }
+      k_bcp<D><<<gw, kBlock, 0, s>>>(W, round);
+    }
+  }
   mark(8);
-  k_bcp<D><<<gw, kBlock, 0, s>>>(W);
-  mark(9);
   k_relabel_min<<<gc, kBlock, 0, s>>>(W);
   k_cell_label<<<gp, kBlock, 0, s>>>(W);
-  mark(10);
+  mark(9);
   k_border<D><<<gw, kBlock, 0, s>>>(W);
-  mark(11);
+  mark(10);
   k_scatter<<<gp, kBlock, 0, s>>>(W);
-  mark(12);
+  mark(11);
   return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
 }
 
@@ -243,6 +259,8 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   std::memset(static_cast<void*>(&W), 0, sizeof(W));
   W.n = (int)n;
   W.minPts = min_pts;
+  W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
+  W.unit_max_level = ctx->unit_level;
   W.E2 = eps * eps;
   W.side = eps / std::sqrt((double)d);
   W.pts = points;
@@ -260,15 +278,16 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   }
   const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
   ctx->events_recorded = ctx->profile;
+  const bool rounds = ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
   switch (d) {
-    case 1: return run<1>(W, s, mark);
-    case 2: return run<2>(W, s, mark);
-    case 3: return run<3>(W, s, mark);
-    case 4: return run<4>(W, s, mark);
-    case 5: return run<5>(W, s, mark);
-    case 6: return run<6>(W, s, mark);
-    case 7: return run<7>(W, s, mark);
-    case 8: return run<8>(W, s, mark);
+    case 1: return run<1>(W, s, mark, rounds);
+    case 2: return run<2>(W, s, mark, rounds);
+    case 3: return run<3>(W, s, mark, rounds);
+    case 4: return run<4>(W, s, mark, rounds);
+    case 5: return run<5>(W, s, mark, rounds);
+    case 6: return run<6>(W, s, mark, rounds);
+    case 7: return run<7>(W, s, mark, rounds);
+    case 8: return run<8>(W, s, mark, rounds);
   }
   return DBSCAN_EINVAL;
 }
@@ -293,6 +312,35 @@ int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
   if (g.status & DBSCAN_STATUS_NONFINITE) return DBSCAN_ENONFINITE;
   if (g.status & DBSCAN_STATUS_WAIT_EXPIRED) return DBSCAN_EINTERNAL;
   return DBSCAN_OK;
+}
+
+int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return DBSCAN_EINVAL;
+  switch (option) {
+    case DBSCAN_OPT_BCP_ROUNDS:
+      if (value < -1 || value > 1) return DBSCAN_EINVAL;
+      ctx->bcp_rounds = (int)value;
+      return DBSCAN_OK;
+    case DBSCAN_OPT_UNIT_LEVEL:
+      if (value < 0 || value > kTreeLevels) return DBSCAN_EINVAL;
+      ctx->unit_level = (int)value;
+      return DBSCAN_OK;
+    case DBSCAN_OPT_FINE_BITS:
+      if (value < -1 || value > 8) return DBSCAN_EINVAL;
+      ctx->fine_bits = (int)value;
+      return DBSCAN_OK;
+  }
+  return DBSCAN_EINVAL;
+}
+
+int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
+  if (!ctx || !value) return DBSCAN_EINVAL;
+  switch (option) {
+    case DBSCAN_OPT_BCP_ROUNDS: *value = ctx->bcp_rounds; return DBSCAN_OK;
+    case DBSCAN_OPT_UNIT_LEVEL: *value = ctx->unit_level; return DBSCAN_OK;
+    case DBSCAN_OPT_FINE_BITS: *value = ctx->fine_bits; return DBSCAN_OK;
+  }
+  return DBSCAN_EINVAL;
 }
 
 int dbscan_set_profiling(dbscan_ctx* ctx, int on) {

@@ -27,6 +27,8 @@ struct TreeView {
 struct Work {
   int n;
   int minPts;
+  int fine_max;       // at most this many sub-cell key bits per dimension
+  int unit_max_level; // largest tree level acting as one ClusterCore unit
   double E2;
   double side;
   const double* pts;  // input, [n][D]
@@ -43,6 +45,9 @@ struct Work {
   uint32_t* idxA;
   uint32_t* idxB;
   double* X;          // [D][n] points in cell order
+  double* chunkLo;    // [D][chunkCap] box of each aligned 64-point chunk of X
+  double* chunkHi;
+  int chunkCap;
   int32_t* perm;      // sorted position -> input index
   int32_t* cellOf;    // [n]
   int32_t* cellStart; // [n+1]
@@ -55,6 +60,8 @@ struct Work {
   int32_t* parent;    // [n] union-find over cells
   int32_t* minIdx;    // [n] per root: smallest input index of a core point
   int32_t* cellLabel; // [n] per cell: cluster id of its core points or -1
+  int32_t* cellMin;   // [n] per cell: smallest input index of its core points
+  int32_t* nroot[kTreeLevels + 1];  // per tree node (levels 1..): common root or -1/-2
   int32_t* blabel;    // [n] border label, cell order
 };
 
@@ -135,17 +142,43 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
 // key only makes cells larger: the diameter guard then splits them into single
 // points, so the result is unchanged.
 template <int D>
-__global__ void k_bbox_final(Work W, int nparts) {
+__global__ __launch_bounds__(kBlock) void k_bbox_final(Work W, int nparts) {
+  __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
+  {
+    double lo[D], hi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lo[k] = __builtin_inf();
+      hi[k] = -__builtin_inf();
+    }
+    for (int j = threadIdx.x; j < nparts; j += kBlock) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        lo[k] = fmin(lo[k], W.bbox_part[j * 2 * kMaxD + k]);
+        hi[k] = fmax(hi[k], W.bbox_part[j * 2 * kMaxD + kMaxD + k]);
+      }
+    }
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double a = wave_min(lo[k]), b = wave_max(hi[k]);
+      if (lane_id() == 0) {
+        s_lo[w][k] = a;
+        s_hi[w][k] = b;
+      }
+    }
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   GridDesc* g = W.desc;
   const bool bad = (g->status & 1u) != 0;
   int len[D];
   int total = 0;
   for (int k = 0; k < D; ++k) {
-    double a = __builtin_inf(), b = -__builtin_inf();
-    for (int j = 0; j < nparts; ++j) {
-      a = fmin(a, W.bbox_part[j * 2 * kMaxD + k]);
-      b = fmax(b, W.bbox_part[j * 2 * kMaxD + kMaxD + k]);
+    double a = s_lo[0][k], b = s_hi[0][k];
+    for (int j = 1; j < kWavesPerBlock; ++j) {
+      a = fmin(a, s_lo[j][k]);
+      b = fmax(b, s_hi[j][k]);
     }
     g->origin[k] = bad ? 0.0 : a;
     len[k] = 0;
@@ -167,25 +200,40 @@ __global__ void k_bbox_final(Work W, int nparts) {
     ++shift;
   }
   for (int k = 0; k < kMaxD; ++k) g->bits[k] = k < D ? max(0, len[k] - shift) : 0;
+  // Sub-cell bits order the points inside each cell along a finer Morton curve, so
+  // that aligned 64-point chunks are spatially compact (tight chunk boxes).
+  int fine = 0;
+  if (shift == 0) fine = max(0, min(W.fine_max, (64 - total) / D));
   g->side = W.side;
   g->shift = shift;
-  g->total_bits = total;
-  g->passes = (total + 7) / 8;
+  g->fine_bits = fine;
+  g->cell_key_shift = fine * D;
+  g->total_bits = total + fine * D;
+  g->passes = (total + fine * D + 7) / 8;
 }
 
 // ---------------------------------------------------------------------------
 // Morton key of every point and the 8-bit digit histograms of all radix passes.
 // ---------------------------------------------------------------------------
 template <int D>
-DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)[D], int maxb) {
+DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)[D], int maxb,
+                           int fine) {
   unsigned long long c[D];
+  unsigned f[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double q = floor(ldexp(floor((x[k] - g->origin[k]) / g->side), -g->shift));
+    const double u = (x[k] - g->origin[k]) / g->side;
+    const double qc = floor(u);
+    const double q = floor(ldexp(qc, -g->shift));
     const unsigned long long lim = bits[k] >= 64 ? ~0ull : ((1ull << bits[k]) - 1ull);
     unsigned long long v = q > 0.0 ? (unsigned long long)q : 0ull;
     if (!(q < 18446744073709551616.0)) v = lim;
     c[k] = v > lim ? lim : v;
+    // position inside the cell, in 2^fine steps (u - floor(u) is exact)
+    const double fr = ldexp(u - qc, fine);
+    const unsigned flim = (1u << fine) - 1u;
+    unsigned fv = fr > 0.0 ? (unsigned)fmin(fr, (double)flim) : 0u;
+    f[k] = fv > flim ? flim : fv;
   }
   uint64_t key = 0;
   for (int b = maxb - 1; b >= 0; --b) {
@@ -193,6 +241,10 @@ DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)
     for (int k = 0; k < D; ++k) {
       if (b < bits[k]) key = (key << 1) | ((c[k] >> b) & 1ull);
     }
+  }
+  for (int b = fine - 1; b >= 0; --b) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) key = (key << 1) | ((f[k] >> b) & 1u);
   }
   return key;
 }
@@ -211,11 +263,12 @@ __global__ __launch_bounds__(kBlock) void k_keys(Work W) {
     maxb = max(maxb, bits[k]);
   }
   const int passes = g->passes;
+  const int fine = g->fine_bits;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
     double x[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = W.pts[(size_t)i * D + k];
-    const uint64_t key = morton_key<D>(x, g, bits, maxb);
+    const uint64_t key = morton_key<D>(x, g, bits, maxb, fine);
     W.keyA[i] = key;
     W.idxA[i] = (uint32_t)i;
     for (int p = 0; p < passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255], 1u);
@@ -357,6 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
   __syncthreads();
   const int tile = s_tile;
   const uint32_t epoch = epoch_of(g, 8 + mode);
+  const int cks = g->cell_key_shift;
 
   bool head[kSortItems];
   uint32_t pre[kSortItems];
@@ -369,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
       if (i == 0) {
         h = true;
       } else if (mode == 0) {
-        h = keys[i] != keys[i - 1];
+        h = (keys[i] >> cks) != (keys[i - 1] >> cks);
       } else {
         const int c = W.cellOf[i];
         h = c != W.cellOf[i - 1] || W.unsafe[c];
@@ -492,6 +546,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
         } else {
           atomic_min_double(&lo[(size_t)k * n + c], a);
           atomic_max_double(&hi[(size_t)k * n + c], b);
+        }
+      }
+      if (!only_if_split) {
+        // box of the whole aligned chunk (independent of cell boundaries)
+        const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
+        const double ca = wave_min(valid ? x : __builtin_inf());
+        const double cb = wave_max(valid ? x : -__builtin_inf());
+        if (lane == 0) {
+          W.chunkLo[(size_t)k * W.chunkCap + ch] = ca;
+          W.chunkHi[(size_t)k * W.chunkCap + ch] = cb;
         }
       }
     }
