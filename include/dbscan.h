@@ -139,11 +139,14 @@ const char *dbscan_phase_name(int32_t phase);
  *                          unit (0..5, default 1)
  *   DBSCAN_OPT_FINE_BITS   sub-cell Morton bits per dimension used to order the
  *                          points inside a cell (-1: automatic = 0, else 0..8)
+ *   DBSCAN_OPT_FORCE_RECHECK  1: the float32 filter sends every pair to the
+ *                          float64 recheck (for testing; default 0)
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
 #define DBSCAN_OPT_UNIT_LEVEL 2
 #define DBSCAN_OPT_FINE_BITS 3
+#define DBSCAN_OPT_FORCE_RECHECK 4
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

@@ -23,7 +23,7 @@ EHIP = -3
 ENONFINITE = -4
 EINTERNAL = -5
 
-OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3}
+OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1

@@ -162,22 +162,11 @@ DB_DEV void load_box(const TreeView& T, int c, Query<D>& q) {
 // the smaller with a CAS on the root, and path halving only ever stores an
 // ancestor, so racing finds and links stay consistent.
 // ---------------------------------------------------------------------------
-#ifndef DB_UF_COHERENT
-#define DB_UF_COHERENT 1
-#endif
-DB_DEV int uf_load(const int32_t* p) {
-#if DB_UF_COHERENT
-  return ld_acq(p);
-#else
-  return *(volatile const int32_t*)p;
-#endif
-}
-
 DB_DEV int uf_find(int32_t* parent, int x) {
   while (true) {
-    const int p = uf_load(&parent[x]);
+    const int p = ld_acq(&parent[x]);
     if (p == x) return x;
-    const int gp = uf_load(&parent[p]);
+    const int gp = ld_acq(&parent[p]);
     if (gp != p) st_rel(&parent[x], gp);
     x = gp;
   }
@@ -200,13 +189,60 @@ DB_DEV bool uf_link(int32_t* parent, int a, int b) {
 }
 
 // ---------------------------------------------------------------------------
+// Pair decisions.  Float64 mode: D(p, q) <= E2 directly.  Float32 filter mode:
+// decide32 on cell-local float32 coordinates; pairs in the error band are decided
+// again in float64 from the float64 coordinates (and counted).
+// ---------------------------------------------------------------------------
+template <int D>
+DB_DEV void load_local(const float* X32, int n, int q, float (&a)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) a[k] = X32[(size_t)k * n + q];
+}
+
+template <int D>
+DB_DEV void load_anchor(const TreeView& T, int c, double (&a)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) a[k] = T.lo[0][(size_t)k * T.cap[0] + c];
+}
+
+// T = fl32(fl64(A_g - A_h)) for the anchor A_g of p's cell and q's cell h.
+template <int D>
+DB_DEV void anchor_offsets(const TreeView& T, const double (&ag)[D], int h, float (&off)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) off[k] = (float)(ag[k] - T.lo[0][(size_t)k * T.cap[0] + h]);
+}
+
+template <int D>
+DB_DEV bool recheck64(const Work* W, int pi, int qi) {
+  double a[D], b[D];
+  load_point<D>(W->X, W->n, pi, a);
+  load_point<D>(W->X, W->n, qi, b);
+  return sqdist<D>(a, b) <= W->E2;
+}
+
+// One pair per lane in filter mode: p (index pi, coordinates ap) broadcast, q per
+// lane.  Returns whether q is within eps of p; band lanes are rechecked.
+template <int D>
+DB_DEV bool filtered_hit(const Work* W, bool valid, const float (&ap)[D], const float (&aq)[D],
+                         const float (&off)[D], float tin, float tout, int pi, int qi) {
+  const int cls = valid ? decide32<D>(ap, aq, off, tin, tout) : 0;
+  bool hit = cls == 1;
+  const uint64_t bm = ballot(cls == 2);
+  if (bm) {
+    if (cls == 2) hit = recheck64<D>(W, pi, qi);
+    if (lane_id() == 0) atomicAdd(&W->desc->rechecks, (unsigned long long)__popcll(bm));
+  }
+  return hit;
+}
+
+// ---------------------------------------------------------------------------
 // MarkCore (Algorithm 2).  A cell with at least minPts points is all core (its
 // points are pairwise within eps: the diameter guard holds for every cell after
 // splitting).  Otherwise each point starts from |g| and adds the points within
 // eps in neighbour cells; it stops as soon as minPts is reached (early exit; the
 // result is the same as counting everything).
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool F32>
 struct MarkCoreVisitor {
   static constexpr bool kNearestFirst = true;
   DB_DEV bool keep_node(int, int) const { return true; }
@@ -215,7 +251,10 @@ struct MarkCoreVisitor {
   int g, ps, pm;
   int cnt;           // lane t: count of point ps + t
   uint64_t pending;  // points of the batch still below minPts
-  double p[D];       // lane t: coordinates of point ps + t
+  double p[D];       // lane t: coordinates of point ps + t (float64 mode)
+  float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
+  double ag[D];      // anchor of g (filter mode)
+  float tin, tout;
 
   DB_DEV bool group(int cb, uint64_t m) {
     if (g >= cb && g < cb + 64) m &= ~(1ull << (g - cb));
@@ -226,23 +265,40 @@ struct MarkCoreVisitor {
     for (int base = 0; base < tot; base += kWave) {
       const int k = base + lane;
       const bool valid = k < tot;
+      int j = 0, q = 0;
       double xq[D];
-      if (valid) {
-        int j, q;
-        locate(F, k, j, q);
-        load_point<D>(W->X, n, q, xq);
-      } else {
+      float aq[D], off[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) xq[d] = 0.0;
+      for (int d = 0; d < D; ++d) {
+        xq[d] = 0.0;
+        aq[d] = 0.0f;
+        off[d] = 0.0f;
+      }
+      if (valid) {
+        locate(F, k, j, q);
+        if constexpr (F32) {
+          load_local<D>(W->X32, n, q, aq);
+          anchor_offsets<D>(W->tree, ag, cb + j, off);
+        } else {
+          load_point<D>(W->X, n, q, xq);
+        }
       }
       uint64_t pend = pending;
       while (pend) {
         const int t = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
-        double xp[D];
+        bool hit;
+        if constexpr (F32) {
+          float at[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
-        const bool hit = valid && sqdist<D>(xp, xq) <= W->E2;
+          for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q);
+        } else {
+          double xp[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
+          hit = valid && sqdist<D>(xp, xq) <= W->E2;
+        }
         const int add = __popcll(ballot(hit));
         if (lane == t) cnt += add;
         const int ct = bcast(cnt, t);
@@ -256,7 +312,7 @@ struct MarkCoreVisitor {
 
 // Besides the core flags, each cell's wave records its number of core points and
 // the smallest input index among them, and initialises the union-find entry.
-template <int D>
+template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
@@ -278,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       q.E2 = W.E2;
       load_box<D>(W.tree, g, q);
       for (int ps = s; ps < e; ps += kWave) {
-        MarkCoreVisitor<D> v;
+        MarkCoreVisitor<D, F32> v;
         v.W = &W;
         v.F = Flat{s_pref[w], s_start[w]};
         v.g = g;
@@ -286,11 +342,18 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
         v.pm = min(kWave, e - ps);
         v.cnt = m;
         v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
-        if (lane < v.pm) load_point<D>(W.X, n, ps + lane, v.p);
-        else {
+        v.tin = W.desc->tin;
+        v.tout = W.desc->tout;
 #pragma unroll
-          for (int d = 0; d < D; ++d) v.p[d] = 0.0;
+        for (int d = 0; d < D; ++d) {
+          v.p[d] = 0.0;
+          v.ap[d] = 0.0f;
         }
+        if (lane < v.pm) {
+          if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
+          else load_point<D>(W.X, n, ps + lane, v.p);
+        }
+        if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
         walk<D>(W.tree, C, q, v);
         const bool core = lane < v.pm && v.cnt >= W.minPts;
         if (lane < v.pm) W.coreS[ps + lane] = core ? 1 : 0;
@@ -319,9 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
 // filter), and 64 x 64 tiles whose chunk boxes are farther than eps apart are
 // skipped whole.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool F32>
 struct BcpVisitor {
   static constexpr bool kNearestFirst = false;
+  float tin, tout;
   const Work* W;
   Flat F;
   int ps, pe;      // sorted point range of the unit (its core points take part)
@@ -367,14 +431,19 @@ struct BcpVisitor {
       bool valid = k < tot;
       int j = 0, q = 0;
       double xq[D];
+      float aq[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) xq[d] = 0.0;
+      for (int d = 0; d < D; ++d) {
+        xq[d] = 0.0;
+        aq[d] = 0.0f;
+      }
       if (valid) {
         locate(F, k, j, q);
         valid = W->coreS[q] != 0 && ((alive >> j) & 1ull);
       }
       if (valid) {
         load_point<D>(W->X, n, q, xq);
+        if constexpr (F32) load_local<D>(W->X32, n, q, aq);
         // points of h farther than eps from the unit's box drop out
         valid = box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
       }
@@ -397,23 +466,53 @@ struct BcpVisitor {
         while (sm && !stop) {
           const int b = __ffsll((long long)sm) - 1;
           sm &= sm - 1;
-          const int i = (c0 + pc0 + b) * kWave + lane;
+          const int chunk = c0 + pc0 + b;
+          const int i = chunk * kWave + lane;
           bool pv = i >= ps && i < pe && W->coreS[i] != 0;
           double xp[D];
+          float ap[D];
+          int pcell = -1;
 #pragma unroll
-          for (int d = 0; d < D; ++d) xp[d] = 0.0;
+          for (int d = 0; d < D; ++d) {
+            xp[d] = 0.0;
+            ap[d] = 0.0f;
+          }
           if (pv) {
-            load_point<D>(W->X, n, i, xp);
-            pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
+            if constexpr (F32) {
+              load_local<D>(W->X32, n, i, ap);
+              pcell = W->cellOf[i];
+            } else {
+              load_point<D>(W->X, n, i, xp);
+              pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
+            }
           }
           uint64_t pm = ballot(pv);
+          int curcell = -1;
+          float off[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) off[d] = 0.0f;
           while (pm) {
             const int t = __ffsll((long long)pm) - 1;
             pm &= pm - 1;
-            double xt[D];
+            bool hit;
+            if constexpr (F32) {
+              const int pc = bcast(pcell, t);
+              if (pc != curcell) {
+                curcell = pc;
+                double apc[D];
+                load_anchor<D>(W->tree, pc, apc);
+                anchor_offsets<D>(W->tree, apc, cb + j, off);
+              }
+              float at[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
-            const bool hit = valid && sqdist<D>(xt, xq) <= W->E2;
+              for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+              hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q);
+            } else {
+              double xt[D];
+#pragma unroll
+              for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
+              hit = valid && sqdist<D>(xt, xq) <= W->E2;
+            }
             if (!ballot(hit)) continue;
             uint64_t cells = wave_or(hit ? (1ull << j) : 0ull);
             while (cells) {
@@ -446,7 +545,7 @@ struct BcpVisitor {
 // acts as a single unit (its first cell's wave runs it), instead of each of its
 // cells repeating the same links.
 // round = -1: a single pass in which every core cell walks the whole tree.
-template <int D>
+template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
@@ -466,10 +565,12 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
       if (W.nroot[l][idx] >= 0 && (l == umax || W.nroot[l + 1][g >> (6 * (l + 1))] < 0)) ulevel = l;
     }
     if (ulevel < 0) continue;
-    BcpVisitor<D> v;
+    BcpVisitor<D, F32> v;
     v.W = &W;
     v.F = Flat{s_pref[w], s_start[w]};
     v.uq.E2 = W.E2;
+    v.tin = W.desc->tin;
+    v.tout = W.desc->tout;
     if (ulevel == 0) {
       v.ps = W.cellStart[g];
       v.pe = W.cellStart[g + 1];
@@ -568,7 +669,7 @@ __global__ void k_cell_label(Work W) {
 // cell share one id, so a neighbour cell whose id is not below the current best
 // is skipped without distance tests.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool F32>
 struct BorderVisitor {
   static constexpr bool kNearestFirst = false;
   DB_DEV bool keep_node(int, int) const { return true; }
@@ -576,7 +677,11 @@ struct BorderVisitor {
   Flat F;
   int g, pm;
   int best;          // lane t: best id so far for batch point t
-  double p[D];       // lane t: coordinates of batch point t
+  int pidx;          // lane t: sorted position of batch point t
+  double p[D];       // lane t: coordinates of batch point t (float64 mode)
+  float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
+  double ag[D];      // anchor of g (filter mode)
+  float tin, tout;
 
   DB_DEV bool group(int cb, uint64_t m) {
     const int lane = lane_id();
@@ -596,25 +701,42 @@ struct BorderVisitor {
       bool valid = k < tot;
       int j = 0, q = 0, lq = kIntMax;
       double xq[D];
+      float aq[D], off[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        xq[d] = 0.0;
+        aq[d] = 0.0f;
+        off[d] = 0.0f;
+      }
       if (valid) {
         locate(F, k, j, q);
         valid = W->coreS[q] != 0;
       }
       if (valid) {
         lq = W->cellLabel[cb + j];
-        load_point<D>(W->X, n, q, xq);
-      } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) xq[d] = 0.0;
+        if constexpr (F32) {
+          load_local<D>(W->X32, n, q, aq);
+          anchor_offsets<D>(W->tree, ag, cb + j, off);
+        } else {
+          load_point<D>(W->X, n, q, xq);
+        }
       }
       for (int t = 0; t < pm; ++t) {
         const int bt = bcast(best, t);
         const bool cand = valid && lq < bt;
         if (!ballot(cand)) continue;
-        double xp[D];
+        bool hit;
+        if constexpr (F32) {
+          float at[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
-        const bool hit = cand && sqdist<D>(xp, xq) <= W->E2;
+          for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+          hit = filtered_hit<D>(W, cand, at, aq, off, tin, tout, bcast(pidx, t), q);
+        } else {
+          double xp[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
+          hit = cand && sqdist<D>(xp, xq) <= W->E2;
+        }
         const int mn = wave_min(hit ? lq : kIntMax);
         if (lane == t && mn < best) best = mn;
       }
@@ -623,7 +745,7 @@ struct BorderVisitor {
   }
 };
 
-template <int D>
+template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_border(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
@@ -663,17 +785,25 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
       const int pos = lane < taken ? s_pos[w][lane] : -1;
       wave_sync();
       if (taken == 0) break;
-      BorderVisitor<D> v;
+      BorderVisitor<D, F32> v;
       v.W = &W;
       v.F = Flat{s_pref[w], s_start[w]};
       v.g = g;
       v.pm = taken;
       v.best = own;
-      if (lane < taken) load_point<D>(W.X, n, pos, v.p);
-      else {
+      v.pidx = pos;
+      v.tin = W.desc->tin;
+      v.tout = W.desc->tout;
 #pragma unroll
-        for (int d = 0; d < D; ++d) v.p[d] = 0.0;
+      for (int d = 0; d < D; ++d) {
+        v.p[d] = 0.0;
+        v.ap[d] = 0.0f;
       }
+      if (lane < taken) {
+        if constexpr (F32) load_local<D>(W.X32, n, pos, v.ap);
+        else load_point<D>(W.X, n, pos, v.p);
+      }
+      if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk<D>(W.tree, C, q, v);
       if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
     }

@@ -30,6 +30,8 @@ struct GridDesc {
   int32_t n_cells;        // C before/after splitting
   int32_t n_unsafe;       // cells whose float64 diameter test failed
   int32_t n_core;
+  unsigned long long max_extent_bits;  // largest cell extent (float64 bits, >= 0)
+  float tin, tout;        // float32 filter thresholds (IN if <= tin, OUT if > tout)
   unsigned long long bcp_calls;
   unsigned long long uf_links;
   unsigned long long rechecks;
@@ -65,6 +67,10 @@ DB_DEV double bcast(double v, int t) {
 
 DB_DEV int bcast(int v, int t) {
   return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(t));
+}
+
+DB_DEV float bcast(float v, int t) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), __builtin_amdgcn_readfirstlane(t)));
 }
 
 DB_DEV int wave_incl_scan(int v) {
@@ -160,6 +166,24 @@ DB_DEV double sqdist(const double (&p)[D], const double (&q)[D]) {
     acc = acc + t * t;
   }
   return acc;
+}
+
+// Float32 filter.  a and b are float32 coordinates of p and q relative to the
+// float64 anchors A_g, A_h of their cells, T = fl32(fl64(A_g - A_h)); the value
+// computed is fl32 of sum_k (fl32(fl32(a_k - b_k) + T_k))^2, in any order with
+// fused multiply-adds allowed (its error bound covers that).  Returns 1 (within
+// eps), 0 (not within) or 2 (inside the error band: decide again in float64).
+template <int D>
+DB_DEV int decide32(const float (&a)[D], const float (&b)[D], const float (&T)[D], float tin,
+                    float tout) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float s1 = a[k] - b[k];
+    const float df = s1 + T[k];
+    acc = __builtin_fmaf(df, df, acc);
+  }
+  return acc <= tin ? 1 : (acc > tout ? 0 : 2);
 }
 
 // Lower bound of D(p, q) over p in box [alo, ahi] and q in box [blo, bhi].

@@ -23,6 +23,7 @@ struct dbscan_ctx {
   int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
   int unit_level = 1;
   int fine_bits = -1;   // -1: automatic (0)
+  int force_recheck = 0;
   bool profile = false;
   bool events_ready = false;
   bool events_recorded = false;
@@ -64,6 +65,7 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   w.idxA = c.take<uint32_t>(n);
   w.idxB = c.take<uint32_t>(n);
   w.X = c.take<double>(n * d);
+  w.X32 = c.take<float>(n * d);
   w.chunkCap = (int)ceil_div(n, 64);
   w.chunkLo = c.take<double>((int64_t)w.chunkCap * d);
   w.chunkHi = c.take<double>((int64_t)w.chunkCap * d);
@@ -130,8 +132,8 @@ struct Marks {
   }
 };
 
-template <int D>
-int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
+template <int D, bool F32>
+int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds, double eps) {
   const int64_t n = W.n;
   const unsigned gp = grid_for(n, kBlock, 2048);           // one thread per point
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);   // one wave per cell
@@ -163,25 +165,29 @@ int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
     const int64_t nodes = W.tree.cap[l];
     k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
   }
+  if (F32) {
+    k_thresholds<D><<<1, 64, 0, s>>>(W, eps);
+    k_local32<D><<<gp, kBlock, 0, s>>>(W);
+  }
   mark(6);
-  k_markcore<D><<<gw, kBlock, 0, s>>>(W);
+  k_markcore<D, F32><<<gw, kBlock, 0, s>>>(W);
   mark(7);
   if (!rounds) {
-    k_bcp<D><<<gw, kBlock, 0, s>>>(W, -1);
+    k_bcp<D, F32><<<gw, kBlock, 0, s>>>(W, -1);
   } else {
     for (int round = 0; round < kTreeLevels; ++round) {
       if (round > 0) {
         for (int l = 1; l <= kTreeLevels; ++l)
           k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
       }
-      k_bcp<D><<<gw, kBlock, 0, s>>>(W, round);
+      k_bcp<D, F32><<<gw, kBlock, 0, s>>>(W, round);
     }
   }
   mark(8);
   k_relabel_min<<<gc, kBlock, 0, s>>>(W);
   k_cell_label<<<gp, kBlock, 0, s>>>(W);
   mark(9);
-  k_border<D><<<gw, kBlock, 0, s>>>(W);
+  k_border<D, F32><<<gw, kBlock, 0, s>>>(W);
   mark(10);
   k_scatter<<<gp, kBlock, 0, s>>>(W);
   mark(11);
@@ -245,7 +251,7 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
            void* stream) {
   if (!ctx || n < 0 || n > DBSCAN_MAX_N || d < 1 || d > DBSCAN_MAX_D) return DBSCAN_EINVAL;
   if (!(eps > 0.0) || !std::isfinite(eps) || min_pts < 1) return DBSCAN_EINVAL;
-  if (mode != DBSCAN_PLAIN_FP64) return DBSCAN_EINVAL;
+  if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
   if (n == 0) {
     ctx->last_n = 0;
     return DBSCAN_OK;
@@ -261,6 +267,7 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   W.minPts = min_pts;
   W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
   W.unit_max_level = ctx->unit_level;
+  W.force_recheck = ctx->force_recheck;
   W.E2 = eps * eps;
   W.side = eps / std::sqrt((double)d);
   W.pts = points;
@@ -279,16 +286,22 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
   ctx->events_recorded = ctx->profile;
   const bool rounds = ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
+  const bool f32 = mode == DBSCAN_FP32_FILTER;
+#define DB_RUN(DD)                                                   \
+  case DD:                                                           \
+    return f32 ? run<DD, true>(W, s, mark, rounds, eps)              \
+               : run<DD, false>(W, s, mark, rounds, eps);
   switch (d) {
-    case 1: return run<1>(W, s, mark, rounds);
-    case 2: return run<2>(W, s, mark, rounds);
-    case 3: return run<3>(W, s, mark, rounds);
-    case 4: return run<4>(W, s, mark, rounds);
-    case 5: return run<5>(W, s, mark, rounds);
-    case 6: return run<6>(W, s, mark, rounds);
-    case 7: return run<7>(W, s, mark, rounds);
-    case 8: return run<8>(W, s, mark, rounds);
+    DB_RUN(1)
+    DB_RUN(2)
+    DB_RUN(3)
+    DB_RUN(4)
+    DB_RUN(5)
+    DB_RUN(6)
+    DB_RUN(7)
+    DB_RUN(8)
   }
+#undef DB_RUN
   return DBSCAN_EINVAL;
 }
 
@@ -329,6 +342,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value < -1 || value > 8) return DBSCAN_EINVAL;
       ctx->fine_bits = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_FORCE_RECHECK:
+      if (value != 0 && value != 1) return DBSCAN_EINVAL;
+      ctx->force_recheck = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -339,6 +356,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_BCP_ROUNDS: *value = ctx->bcp_rounds; return DBSCAN_OK;
     case DBSCAN_OPT_UNIT_LEVEL: *value = ctx->unit_level; return DBSCAN_OK;
     case DBSCAN_OPT_FINE_BITS: *value = ctx->fine_bits; return DBSCAN_OK;
+    case DBSCAN_OPT_FORCE_RECHECK: *value = ctx->force_recheck; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

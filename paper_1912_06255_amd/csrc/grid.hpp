@@ -29,6 +29,7 @@ struct Work {
   int minPts;
   int fine_max;       // at most this many sub-cell key bits per dimension
   int unit_max_level; // largest tree level acting as one ClusterCore unit
+  int force_recheck;  // filter mode: decide every pair in float64
   double E2;
   double side;
   const double* pts;  // input, [n][D]
@@ -45,6 +46,7 @@ struct Work {
   uint32_t* idxA;
   uint32_t* idxB;
   double* X;          // [D][n] points in cell order
+  float* X32;         // [D][n] float32 coordinates relative to the cell anchor (filter mode)
   double* chunkLo;    // [D][chunkCap] box of each aligned 64-point chunk of X
   double* chunkHi;
   int chunkCap;
@@ -85,6 +87,7 @@ __global__ void k_init(Work W) {
     g->n_cells = 0;
     g->n_unsafe = 0;
     g->n_core = 0;
+    g->max_extent_bits = 0;
     g->bcp_calls = 0;
     g->uf_links = 0;
     g->rechecks = 0;
@@ -570,6 +573,7 @@ __global__ void k_cell_safe(Work W) {
   GridDesc* g = W.desc;
   const int C = g->n_cells, n = W.n;
   int bad = 0;
+  double ext = 0.0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
     double a[D], b[D];
 #pragma unroll
@@ -580,9 +584,67 @@ __global__ void k_cell_safe(Work W) {
     const bool uns = !(sqdist<D>(a, b) <= W.E2);
     W.unsafe[c] = uns;
     bad += uns;
+#pragma unroll
+    for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
   }
   bad = wave_sum(bad);
+  ext = wave_max(ext);
   if (lane_id() == 0 && bad) atomicAdd(&g->n_unsafe, bad);
+  // extents are >= 0, so their bit patterns order like the values
+  if (lane_id() == 0 && ext > 0.0)
+    atomicMax(&g->max_extent_bits, (unsigned long long)__double_as_longlong(ext));
+}
+
+// Float32 filter thresholds (see decide32).  With u = 2^-24, v = 2^-53,
+// M = largest cell extent (bounds |coordinate - anchor|) and
+// Tm = eps (1 + 2^-20) + 2 M (bounds |T| for every pair near the eps boundary),
+// each float32 coordinate difference is within
+//   eta = (1 + 2^-20) u (6 M + 2 Tm)
+// of the exact difference (five roundings: the two stored coordinates, T, the
+// subtraction and the addition; the factor absorbs the u^2 and v terms).  The
+// float32 sum of squares is within gamma_d = d u / (1 - d u) of its exact value,
+// and the defined float64 D within gammabar = (d+2) v / (1 - (d+2) v) of the exact
+// squared distance S.  Hence
+//   D32 <= T_in  = (1 - gamma_d) (sqrt(E2 / (1 + gammabar)) - sqrt(d) eta)^2  =>  D <= E2
+//   D32 >  T_out = (1 + gamma_d) (sqrt(E2 / (1 - gammabar)) + sqrt(d) eta)^2  =>  D >  E2.
+// Both are widened by 2^-40 for the rounding of this computation and rounded
+// outwards to float32.  Outside a safe exponent range every pair is rechecked.
+template <int D>
+__global__ void k_thresholds(Work W, double eps) {
+  if (threadIdx.x != 0) return;
+  GridDesc* g = W.desc;
+  const double u = 0x1p-24, v = 0x1p-53;
+  const double M = __longlong_as_double((long long)g->max_extent_bits) * (1.0 + 0x1p-40);
+  const double gd = D * u / (1.0 - D * u);
+  const double gb = (D + 2) * v / (1.0 - (D + 2) * v);
+  const double Tm = eps * (1.0 + 0x1p-20) + 2.0 * M;
+  const double eta = (1.0 + 0x1p-20) * u * (6.0 * M + 2.0 * Tm);
+  const double r = sqrt((double)D) * eta * (1.0 + 0x1p-40);
+  const double E2 = W.E2;
+  const double ain = sqrt(E2 / (1.0 + gb)) * (1.0 - 0x1p-40) - r;
+  const double aout = sqrt(E2 / (1.0 - gb)) * (1.0 + 0x1p-40) + r;
+  double tin = ain > 0.0 ? (1.0 - gd) * ain * ain * (1.0 - 0x1p-40) : -1.0;
+  double tout = (1.0 + gd) * aout * aout * (1.0 + 0x1p-40);
+  const bool ok = E2 >= 0x1p-100 && E2 <= 0x1p100 && (eps + 2.0 * M) <= 0x1p60 &&
+                  __builtin_isfinite(tout) && g->status == 0;
+  if (!ok || W.force_recheck) {
+    tin = -__builtin_inf();
+    tout = __builtin_inf();
+  }
+  g->tin = __double2float_rd(tin);
+  g->tout = __double2float_ru(tout);
+}
+
+// Float32 coordinates relative to the anchor of each point's cell (its box corner).
+template <int D>
+__global__ void k_local32(Work W) {
+  const int n = W.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c = W.cellOf[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      W.X32[(size_t)k * n + i] = (float)(W.X[(size_t)k * n + i] - W.tree.lo[0][(size_t)k * n + c]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ from workloads import blobs_2d, config_workload, gaussian_mixture, multi_cloud_b
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["fp64"]
+MODES = ["fp64", "fp32_filter"]
 
 
 def _impl(mode):
@@ -186,3 +186,58 @@ def test_full_size_against_oracle_hash(name, mode, gpu_lib):
     }
     assert summary == {k: case[k] for k in summary}, (summary, case)
     assert digest(core, lab) == case["sha256"]
+
+
+def _set_opts(**kw):
+    from paper_1912_06255_amd import binding
+
+    for k, v in kw.items():
+        binding.set_option(k, v)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 7])
+def test_filter_forced_recheck_equals_plain(d, gpu_lib):
+    """With every pair sent to the float64 recheck the filter path must equal plain."""
+    rng = np.random.Generator(np.random.PCG64(301 + d))
+    X = gaussian_mixture(6000, d, 10, 1.0, 12.0, 0.05, rng)
+    eps = 1.2 if d <= 3 else 2.0
+    plain, st0 = gpu_dbscan(X, eps, 8, mode="fp64", tag=f"plain d={d}", want_stats=True)
+    try:
+        _set_opts(force_recheck=1)
+        forced, st1 = gpu_dbscan(X, eps, 8, mode="fp32_filter", tag=f"forced d={d}", want_stats=True)
+    finally:
+        _set_opts(force_recheck=0)
+    assert st1["fp64_rechecks"] > 0
+    assert np.array_equal(plain[0], forced[0]) and np.array_equal(plain[1], forced[1])
+
+
+def test_filter_rechecks_exact_boundaries(gpu_lib):
+    """Integer lattice with eps = 1: every axis pair sits exactly at eps, so the
+    float32 band must send them to float64 and the result must stay exact."""
+    rng = np.random.Generator(np.random.PCG64(302))
+    P = rng.integers(0, 40, size=(30000, 3)).astype(np.float64)
+    want = dbscan_o1(P, 1.0, 4)
+    got, st = gpu_dbscan(P, 1.0, 4, mode="fp32_filter", tag="lattice filter", want_stats=True)
+    assert st["fp64_rechecks"] > 0, st
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+@pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
+                                  dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
+                                  dict(fine_bits=3), dict(fine_bits=0)])
+@pytest.mark.parametrize("mode", MODES)
+def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
+    n = 40_000
+    X = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=303)
+    rng = np.random.Generator(np.random.PCG64(304))
+    Y = gaussian_mixture(8000, 5, 10, 1.0, 12.0, 0.05, rng)
+    wantX = dbscan_o1(X, 200.0, 10)
+    wantY = dbscan_o1(Y, 2.0, 10)
+    try:
+        _set_opts(**opts)
+        gx = gpu_dbscan(X, 200.0, 10, mode=mode, tag=f"opts {opts} 3d")
+        gy = gpu_dbscan(Y, 2.0, 10, mode=mode, tag=f"opts {opts} 5d")
+    finally:
+        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1)
+    assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
+    assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
