@@ -104,6 +104,42 @@ int dbscan(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d, double e
            int32_t min_pts, int32_t mode, uint8_t *core_flags, int32_t *cluster_id,
            void *stream);
 
+/*
+ * A batch: many point clouds, each with one or more (eps, minPts) settings
+ * (paper, Algorithm 1 run once per cloud and setting).  Results are identical to
+ * one dbscan() call per (cloud, setting).
+ *   points       device, float64 [n][d] row-major
+ *   n, d         as for dbscan() (n = 0 allowed)
+ *   n_settings   >= 1
+ *   eps, min_pts HOST arrays [n_settings]
+ *   core_flags   device, uint8 [n_settings][n]: setting s at core_flags + s*n
+ *   cluster_id   device, int32 [n_settings][n]
+ */
+typedef struct {
+  const double *points;
+  int64_t n;
+  int32_t d;
+  int32_t n_settings;
+  const double *eps;
+  const int32_t *min_pts;
+  uint8_t *core_flags;
+  int32_t *cluster_id;
+} dbscan_instance;
+
+/*
+ * Run a batch on `stream`.  Settings of one cloud with the same eps share its
+ * grid, cell tree and one MarkCore neighbour count (taken up to the largest
+ * minPts of that eps).  With DBSCAN_OPT_BATCH_GRAPH on (the default) the whole
+ * batch is captured into one HIP graph the first time a batch description
+ * (pointers, sizes, settings, mode, options) is seen and replayed as a single
+ * graph launch on later identical calls; the first call also instantiates the
+ * graph.  Scratch is sized for the largest cloud.  Counters read afterwards with
+ * dbscan_get_stats() cover the whole batch (bcp_calls, uf_links, fp64_rechecks,
+ * status) or its last cloud and setting (cells, core points).
+ */
+int dbscan_batch(dbscan_ctx *ctx, const dbscan_instance *inst, int32_t count, int32_t mode,
+                 void *stream);
+
 /* Pre-size the context's scratch for clouds of up to n points of dimension d. */
 int dbscan_reserve(dbscan_ctx *ctx, int64_t n, int32_t d);
 
@@ -141,12 +177,15 @@ const char *dbscan_phase_name(int32_t phase);
  *                          points inside a cell (-1: automatic = 0, else 0..8)
  *   DBSCAN_OPT_FORCE_RECHECK  1: the float32 filter sends every pair to the
  *                          float64 recheck (for testing; default 0)
+ *   DBSCAN_OPT_BATCH_GRAPH 1: dbscan_batch() captures and replays a HIP graph
+ *                          (default); 0: it launches its kernels directly
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
 #define DBSCAN_OPT_UNIT_LEVEL 2
 #define DBSCAN_OPT_FINE_BITS 3
 #define DBSCAN_OPT_FORCE_RECHECK 4
+#define DBSCAN_OPT_BATCH_GRAPH 5
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

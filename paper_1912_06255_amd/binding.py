@@ -23,7 +23,7 @@ EHIP = -3
 ENONFINITE = -4
 EINTERNAL = -5
 
-OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4}
+OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4, "batch_graph": 5}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1
@@ -55,6 +55,19 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("points", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int32),
+        ("n_settings", ctypes.c_int32),
+        ("eps", ctypes.POINTER(ctypes.c_double)),
+        ("min_pts", ctypes.POINTER(ctypes.c_int32)),
+        ("core_flags", ctypes.c_void_p),
+        ("cluster_id", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 _lock = threading.Lock()
 _ctx: dict[int, ctypes.c_void_p] = {}
@@ -76,6 +89,7 @@ def load():
     lib.dbscan_reserve.argtypes = [vp, i64, i32]
     lib.dbscan.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp]
     lib.dbscan_get_stats.argtypes = [vp, vp, ctypes.POINTER(Stats)]
+    lib.dbscan_batch.argtypes = [vp, ctypes.POINTER(Instance), i32, i32, vp]
     lib.dbscan_set_option.argtypes = [vp, i32, i64]
     lib.dbscan_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.dbscan_set_profiling.argtypes = [vp, ctypes.c_int]
@@ -85,7 +99,8 @@ def load():
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
-              "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option"):
+              "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option",
+              "dbscan_batch"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -198,3 +213,50 @@ def get_option(name: str, device: int = 0) -> int:
     v = ctypes.c_int64()
     _check(load().dbscan_get_option(context(device), OPTIONS[name], ctypes.byref(v)), f"get_option {name}")
     return int(v.value)
+
+
+class Batch:
+    """A batch description for dbscan_batch: clouds (float64 CUDA tensors [n, d])
+    with their (eps, minPts) settings.  Output tensors [n_settings, n] are
+    allocated once; keeping the Batch object alive keeps every pointer stable, so
+    repeated run() calls replay the captured graph."""
+
+    def __init__(self, clouds, settings, mode="fp32_filter"):
+        import torch
+
+        if len(clouds) != len(settings):
+            raise ValueError("one settings list per cloud")
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        self.clouds = []
+        self.core = []
+        self.label = []
+        self._keep = []
+        arr = (Instance * len(clouds))()
+        for i, (X, st) in enumerate(zip(clouds, settings)):
+            if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64 and X.dim() == 2):
+                raise TypeError("each cloud must be a float64 CUDA tensor [n, d]")
+            X = X.contiguous()
+            n, d = X.shape
+            eps = (ctypes.c_double * len(st))(*[float(e) for e, _ in st])
+            mp = (ctypes.c_int32 * len(st))(*[int(m) for _, m in st])
+            core = torch.empty((len(st), n), dtype=torch.uint8, device=X.device)
+            lab = torch.empty((len(st), n), dtype=torch.int32, device=X.device)
+            arr[i] = Instance(X.data_ptr(), n, d, len(st), eps, mp, core.data_ptr(), lab.data_ptr())
+            self.clouds.append(X)
+            self.core.append(core)
+            self.label.append(lab)
+            self._keep += [eps, mp]
+        self._arr = arr
+        self.device = self.clouds[0].device.index if self.clouds and self.clouds[0].device.index is not None else 0
+
+    def run(self, stream=None, check: bool = True):
+        rc = load().dbscan_batch(context(self.device), self._arr, len(self.clouds), self.mode,
+                                 _stream_handle(self.device, stream))
+        _check(rc, "dbscan_batch")
+        if check:
+            stats(self.device, stream, raise_on_error=True)
+        return self.core, self.label
+
+    @property
+    def points(self) -> int:
+        return int(sum(X.shape[0] * c.shape[0] for X, c in zip(self.clouds, self.core)))

@@ -302,7 +302,7 @@ struct MarkCoreVisitor {
         const int add = __popcll(ballot(hit));
         if (lane == t) cnt += add;
         const int ct = bcast(cnt, t);
-        if (ct >= W->minPts) pending &= ~(1ull << t);
+        if (ct >= W->count_cap) pending &= ~(1ull << t);
       }
       if (!pending) return true;
     }
@@ -310,8 +310,9 @@ struct MarkCoreVisitor {
   }
 };
 
-// Besides the core flags, each cell's wave records its number of core points and
-// the smallest input index among them, and initialises the union-find entry.
+// Neighbour counts, capped at count_cap (the largest minPts run with this eps, so
+// that one count serves every minPts).  A cell with at least count_cap points
+// needs no test: all its points are pairwise within eps.
 template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
@@ -319,48 +320,62 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
-  int ncore = 0;
+  const int cap = W.count_cap;
   for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
     const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
+    if (m >= cap) {
+      for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
+      continue;
+    }
+    Query<D> q;
+    q.E2 = W.E2;
+    load_box<D>(W.tree, g, q);
+    for (int ps = s; ps < e; ps += kWave) {
+      MarkCoreVisitor<D, F32> v;
+      v.W = &W;
+      v.F = Flat{s_pref[w], s_start[w]};
+      v.g = g;
+      v.ps = ps;
+      v.pm = min(kWave, e - ps);
+      v.cnt = m;
+      v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
+      v.tin = W.desc->tin;
+      v.tout = W.desc->tout;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        v.p[d] = 0.0;
+        v.ap[d] = 0.0f;
+      }
+      if (lane < v.pm) {
+        if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
+        else load_point<D>(W.X, n, ps + lane, v.p);
+      }
+      if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
+      walk<D>(W.tree, C, q, v);
+      if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
+    }
+  }
+}
+
+// Core flags of one minPts from the counts (Algorithm 2's test), the number of
+// core points and the smallest input index among them per cell, and the
+// union-find initialisation.
+__global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
+  const int C = W.desc->n_cells;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int ncore = 0;
+  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+    const int s = W.cellStart[g], e = W.cellStart[g + 1];
     int cc = 0, mn = kIntMax;
-    if (m >= W.minPts) {
-      for (int i = s + lane; i < e; i += kWave) {
-        W.coreS[i] = 1;
+    for (int i = s + lane; i < e; i += kWave) {
+      const bool core = W.cnt[i] >= W.minPts;
+      W.coreS[i] = core ? 1 : 0;
+      if (core) {
+        ++cc;
         mn = min(mn, W.perm[i]);
       }
-      cc = m;
-    } else {
-      Query<D> q;
-      q.E2 = W.E2;
-      load_box<D>(W.tree, g, q);
-      for (int ps = s; ps < e; ps += kWave) {
-        MarkCoreVisitor<D, F32> v;
-        v.W = &W;
-        v.F = Flat{s_pref[w], s_start[w]};
-        v.g = g;
-        v.ps = ps;
-        v.pm = min(kWave, e - ps);
-        v.cnt = m;
-        v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
-        v.tin = W.desc->tin;
-        v.tout = W.desc->tout;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          v.p[d] = 0.0;
-          v.ap[d] = 0.0f;
-        }
-        if (lane < v.pm) {
-          if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
-          else load_point<D>(W.X, n, ps + lane, v.p);
-        }
-        if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-        walk<D>(W.tree, C, q, v);
-        const bool core = lane < v.pm && v.cnt >= W.minPts;
-        if (lane < v.pm) W.coreS[ps + lane] = core ? 1 : 0;
-        if (core) mn = min(mn, W.perm[ps + lane]);
-        cc += __popcll(ballot(core));
-      }
     }
+    cc = wave_sum(cc);
     mn = wave_min(mn);
     if (lane == 0) {
       W.coreCount[g] = cc;
@@ -371,6 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
     ncore += cc;
   }
   if (lane == 0 && ncore) atomicAdd(&W.desc->n_core, ncore);
+}
+
+__global__ void k_setting_init(Work W) {
+  if (threadIdx.x == 0) W.desc->n_core = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,12 +1,15 @@
-// Host side of the C ABI declared in include/dbscan.h: context, scratch layout and
-// the launch sequence of one exact DBSCAN call (paper, Algorithm 1).
+// Host side of the C ABI declared in include/dbscan.h: context, scratch layout,
+// the launch sequence of one exact DBSCAN (paper, Algorithm 1), and batches of
+// clouds and settings captured into one HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/dbscan.h"
 #include "cluster.hpp"
@@ -20,14 +23,21 @@ struct dbscan_ctx {
   GridDesc* desc = nullptr;  // lives at the start of scratch, survives growth
   size_t desc_bytes = 0;
   int64_t last_n = 0;
+  // tuning options
   int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
   int unit_level = 1;
   int fine_bits = -1;   // -1: automatic (0)
   int force_recheck = 0;
+  int batch_graph = 1;
+  // profiling
   bool profile = false;
   bool events_ready = false;
   bool events_recorded = false;
   hipEvent_t ev[DBSCAN_NUM_PHASES + 1];
+  // captured batch
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<unsigned char> graph_key;
 };
 
 namespace {
@@ -84,6 +94,7 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
     w.nroot[l] = l > 0 ? c.take<int32_t>(cap) : nullptr;
   }
   w.coreS = c.take<uint8_t>(n);
+  w.cnt = c.take<int32_t>(n);
   w.coreCount = c.take<int32_t>(n);
   w.parent = c.take<int32_t>(n);
   w.minIdx = c.take<int32_t>(n);
@@ -91,6 +102,12 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   w.cellMin = c.take<int32_t>(n);
   w.blabel = c.take<int32_t>(n);
   return c.off;
+}
+
+void drop_graph(dbscan_ctx* ctx) {
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+  ctx->graph = nullptr;
+  ctx->graph_key.clear();
 }
 
 int grow(dbscan_ctx* ctx, int64_t n, int d) {
@@ -108,6 +125,7 @@ int grow(dbscan_ctx* ctx, int64_t n, int d) {
     }
     (void)hipFree(ctx->scratch);
   }
+  drop_graph(ctx);  // a captured batch refers to the old scratch
   ctx->scratch = p;
   ctx->scratch_bytes = need;
   ctx->desc = reinterpret_cast<GridDesc*>(p);
@@ -132,17 +150,20 @@ struct Marks {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Launch stages.  grid: cells, boxes, guard, tree (and the float32 coordinates
+// and thresholds); count: MarkCore neighbour counts up to count_cap; setting:
+// core flags of one minPts, ClusterCore, relabel, ClusterBorder, scatter.
+// ---------------------------------------------------------------------------
 template <int D, bool F32>
-int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds, double eps) {
+void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, bool first) {
   const int64_t n = W.n;
-  const unsigned gp = grid_for(n, kBlock, 2048);           // one thread per point
-  const unsigned gw = grid_for(n, kWavesPerBlock, 4096);   // one wave per cell
-  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);  // wave per chunk
+  const unsigned gp = grid_for(n, kBlock, 2048);
+  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
   const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
   const unsigned tiles = (unsigned)ceil_div(n, kTile);
-
   mark(0);
-  k_init<<<1, kBlock, 0, s>>>(W);
+  k_init<<<1, kBlock, 0, s>>>(W, first ? 1 : 0);
   k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W);
   k_bbox_final<D><<<1, kBlock, 0, s>>>(W, (int)nb);
   mark(1);
@@ -170,7 +191,21 @@ int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds, double eps
     k_local32<D><<<gp, kBlock, 0, s>>>(W);
   }
   mark(6);
-  k_markcore<D, F32><<<gw, kBlock, 0, s>>>(W);
+}
+
+template <int D, bool F32>
+void stage_count(const Work& W, hipStream_t s) {
+  k_markcore<D, F32><<<grid_for(W.n, kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
+}
+
+template <int D, bool F32>
+void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
+  const int64_t n = W.n;
+  const unsigned gp = grid_for(n, kBlock, 2048);
+  const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
+  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
+  k_setting_init<<<1, 64, 0, s>>>(W);
+  k_core_from_count<<<gw, kBlock, 0, s>>>(W);
   mark(7);
   if (!rounds) {
     k_bcp<D, F32><<<gw, kBlock, 0, s>>>(W, -1);
@@ -191,7 +226,132 @@ int run(const Work& W, hipStream_t s, const Marks& mark, bool rounds, double eps
   mark(10);
   k_scatter<<<gp, kBlock, 0, s>>>(W);
   mark(11);
+}
+
+struct Stages {
+  void (*grid)(const Work&, hipStream_t, const Marks&, double, bool);
+  void (*count)(const Work&, hipStream_t);
+  void (*setting)(const Work&, hipStream_t, const Marks&, bool);
+};
+
+template <int D, bool F32>
+Stages stages_of() {
+  return Stages{&stage_grid<D, F32>, &stage_count<D, F32>, &stage_setting<D, F32>};
+}
+
+Stages stages_for(int d, bool f32) {
+  switch (d) {
+#define DB_STAGES(DD) \
+  case DD:            \
+    return f32 ? stages_of<DD, true>() : stages_of<DD, false>();
+    DB_STAGES(1)
+    DB_STAGES(2)
+    DB_STAGES(3)
+    DB_STAGES(4)
+    DB_STAGES(5)
+    DB_STAGES(6)
+    DB_STAGES(7)
+    DB_STAGES(8)
+#undef DB_STAGES
+  }
+  return Stages{nullptr, nullptr, nullptr};
+}
+
+// Fields of Work shared by every stage of one grid.
+void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d, double eps) {
+  std::memset(static_cast<void*>(&W), 0, sizeof(W));
+  W.n = (int)n;
+  W.E2 = eps * eps;
+  W.side = eps / std::sqrt((double)d);
+  W.pts = points;
+  W.desc = ctx->desc;
+  W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
+  W.unit_max_level = ctx->unit_level;
+  W.force_recheck = ctx->force_recheck;
+  layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
+}
+
+bool rounds_for(const dbscan_ctx* ctx, int d) {
+  return ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
+}
+
+int check_args(int64_t n, int32_t d, double eps, int32_t min_pts) {
+  if (n < 0 || n > DBSCAN_MAX_N || d < 1 || d > DBSCAN_MAX_D) return DBSCAN_EINVAL;
+  if (!(eps > 0.0) || !std::isfinite(eps) || min_pts < 1) return DBSCAN_EINVAL;
+  return DBSCAN_OK;
+}
+
+// Enqueue a whole batch on stream s (eagerly or under capture).  Settings of one
+// instance with equal eps share the grid and one neighbour count, taken up to the
+// largest of their minPts.
+int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, bool f32,
+                  hipStream_t s) {
+  const Marks none{nullptr, s};
+  bool first = true;
+  for (int32_t i = 0; i < count; ++i) {
+    const dbscan_instance& I = inst[i];
+    if (I.n == 0) continue;
+    const Stages st = stages_for(I.d, f32);
+    const bool rounds = rounds_for(ctx, I.d);
+    std::vector<char> done((size_t)I.n_settings, 0);
+    for (int32_t a = 0; a < I.n_settings; ++a) {
+      if (done[a]) continue;
+      const double eps = I.eps[a];
+      int cap = 0;
+      for (int32_t b = a; b < I.n_settings; ++b)
+        if (I.eps[b] == eps) cap = std::max(cap, (int)I.min_pts[b]);
+      Work W;
+      fill_work(ctx, W, I.points, I.n, I.d, eps);
+      W.count_cap = cap;
+      st.grid(W, s, none, eps, first);
+      first = false;
+      st.count(W, s);
+      for (int32_t b = a; b < I.n_settings; ++b) {
+        if (I.eps[b] != eps) continue;
+        done[b] = 1;
+        Work Ws = W;
+        Ws.minPts = I.min_pts[b];
+        Ws.core_out = I.core_flags + (size_t)b * (size_t)I.n;
+        Ws.label_out = I.cluster_id + (size_t)b * (size_t)I.n;
+        st.setting(Ws, s, none, rounds);
+      }
+    }
+  }
   return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
+template <class T>
+void put(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+// Everything a captured batch depends on.
+std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instance* inst,
+                                     int32_t count, int32_t mode) {
+  std::vector<unsigned char> k;
+  put(k, ctx->scratch);
+  put(k, ctx->scratch_bytes);
+  put(k, mode);
+  put(k, ctx->bcp_rounds);
+  put(k, ctx->unit_level);
+  put(k, ctx->fine_bits);
+  put(k, ctx->force_recheck);
+  put(k, count);
+  for (int32_t i = 0; i < count; ++i) {
+    const dbscan_instance& I = inst[i];
+    put(k, I.points);
+    put(k, I.n);
+    put(k, I.d);
+    put(k, I.n_settings);
+    put(k, I.core_flags);
+    put(k, I.cluster_id);
+    for (int32_t a = 0; a < I.n_settings; ++a) {
+      put(k, I.eps[a]);
+      put(k, I.min_pts[a]);
+    }
+  }
+  return k;
 }
 
 }  // namespace
@@ -234,6 +394,8 @@ int dbscan_ctx_destroy(dbscan_ctx* ctx) {
   int rc = DBSCAN_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) rc = DBSCAN_EHIP;
   if (hipDeviceSynchronize() != hipSuccess) rc = DBSCAN_EHIP;
+  drop_graph(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->scratch && hipFree(ctx->scratch) != hipSuccess) rc = DBSCAN_EHIP;
   if (ctx->events_ready)
     for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i) (void)hipEventDestroy(ctx->ev[i]);
@@ -249,8 +411,9 @@ int dbscan_reserve(dbscan_ctx* ctx, int64_t n, int32_t d) {
 int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
            int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
            void* stream) {
-  if (!ctx || n < 0 || n > DBSCAN_MAX_N || d < 1 || d > DBSCAN_MAX_D) return DBSCAN_EINVAL;
-  if (!(eps > 0.0) || !std::isfinite(eps) || min_pts < 1) return DBSCAN_EINVAL;
+  if (!ctx) return DBSCAN_EINVAL;
+  int rc = check_args(n, d, eps, min_pts);
+  if (rc != DBSCAN_OK) return rc;
   if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
   if (n == 0) {
     ctx->last_n = 0;
@@ -258,24 +421,15 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   }
   if (!points || !core_flags || !cluster_id) return DBSCAN_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
-  int rc = grow(ctx, n, d);
+  rc = grow(ctx, n, d);
   if (rc != DBSCAN_OK) return rc;
 
   Work W;
-  std::memset(static_cast<void*>(&W), 0, sizeof(W));
-  W.n = (int)n;
+  fill_work(ctx, W, points, n, d, eps);
+  W.count_cap = min_pts;
   W.minPts = min_pts;
-  W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
-  W.unit_max_level = ctx->unit_level;
-  W.force_recheck = ctx->force_recheck;
-  W.E2 = eps * eps;
-  W.side = eps / std::sqrt((double)d);
-  W.pts = points;
   W.core_out = core_flags;
   W.label_out = cluster_id;
-  W.desc = ctx->desc;
-  layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
-
   ctx->last_n = n;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (ctx->profile && !ctx->events_ready) {
@@ -285,24 +439,64 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   }
   const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
   ctx->events_recorded = ctx->profile;
-  const bool rounds = ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
-  const bool f32 = mode == DBSCAN_FP32_FILTER;
-#define DB_RUN(DD)                                                   \
-  case DD:                                                           \
-    return f32 ? run<DD, true>(W, s, mark, rounds, eps)              \
-               : run<DD, false>(W, s, mark, rounds, eps);
-  switch (d) {
-    DB_RUN(1)
-    DB_RUN(2)
-    DB_RUN(3)
-    DB_RUN(4)
-    DB_RUN(5)
-    DB_RUN(6)
-    DB_RUN(7)
-    DB_RUN(8)
+  const Stages st = stages_for(d, mode == DBSCAN_FP32_FILTER);
+  st.grid(W, s, mark, eps, true);
+  st.count(W, s);
+  st.setting(W, s, mark, rounds_for(ctx, d));
+  return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
+int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, int32_t mode,
+                 void* stream) {
+  if (!ctx || count < 0 || (count > 0 && !inst)) return DBSCAN_EINVAL;
+  if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
+  int64_t nmax = 0;
+  int32_t dmax = 1;
+  for (int32_t i = 0; i < count; ++i) {
+    const dbscan_instance& I = inst[i];
+    if (I.n_settings < 1 || !I.eps || !I.min_pts) return DBSCAN_EINVAL;
+    for (int32_t a = 0; a < I.n_settings; ++a) {
+      const int rc = check_args(I.n, I.d, I.eps[a], I.min_pts[a]);
+      if (rc != DBSCAN_OK) return rc;
+    }
+    if (I.n > 0 && (!I.points || !I.core_flags || !I.cluster_id)) return DBSCAN_EINVAL;
+    nmax = std::max(nmax, I.n);
+    dmax = std::max(dmax, I.d);
   }
-#undef DB_RUN
-  return DBSCAN_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  int rc = grow(ctx, nmax, dmax);
+  if (rc != DBSCAN_OK) return rc;
+  ctx->events_recorded = false;
+  ctx->last_n = 0;
+  for (int32_t i = 0; i < count; ++i) ctx->last_n += inst[i].n * inst[i].n_settings;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f32 = mode == DBSCAN_FP32_FILTER;
+  if (!ctx->batch_graph) return enqueue_batch(ctx, inst, count, f32, s);
+
+  std::vector<unsigned char> key = batch_key(ctx, inst, count, mode);
+  if (!ctx->graph || key != ctx->graph_key) {
+    drop_graph(ctx);
+    if (!ctx->cap_stream &&
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return DBSCAN_EHIP;
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return DBSCAN_EHIP;
+    rc = enqueue_batch(ctx, inst, count, f32, ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (rc != DBSCAN_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != DBSCAN_OK ? rc : DBSCAN_EHIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      ctx->graph = nullptr;
+      return DBSCAN_EHIP;
+    }
+    ctx->graph_key.swap(key);
+  }
+  return hipGraphLaunch(ctx->graph, s) == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
 }
 
 int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
@@ -312,13 +506,13 @@ int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
   GridDesc g;
   if (hipMemcpy(&g, ctx->desc, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return DBSCAN_EHIP;
   std::memset(out, 0, sizeof(*out));
+  out->n_points = ctx->last_n;
   out->n_cells = g.n_cells;
   out->n_unsafe = g.n_unsafe;
   out->n_core = g.n_core;
   out->bcp_calls = (int64_t)g.bcp_calls;
   out->uf_links = (int64_t)g.uf_links;
   out->fp64_rechecks = (int64_t)g.rechecks;
-  out->n_points = ctx->last_n;
   out->key_bits = g.total_bits;
   out->key_shift = g.shift;
   out->status = g.status;
@@ -346,6 +540,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return DBSCAN_EINVAL;
       ctx->force_recheck = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_BATCH_GRAPH:
+      if (value != 0 && value != 1) return DBSCAN_EINVAL;
+      ctx->batch_graph = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -357,6 +555,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_UNIT_LEVEL: *value = ctx->unit_level; return DBSCAN_OK;
     case DBSCAN_OPT_FINE_BITS: *value = ctx->fine_bits; return DBSCAN_OK;
     case DBSCAN_OPT_FORCE_RECHECK: *value = ctx->force_recheck; return DBSCAN_OK;
+    case DBSCAN_OPT_BATCH_GRAPH: *value = ctx->batch_graph; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

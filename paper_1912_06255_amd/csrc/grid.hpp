@@ -30,6 +30,7 @@ struct Work {
   int fine_max;       // at most this many sub-cell key bits per dimension
   int unit_max_level; // largest tree level acting as one ClusterCore unit
   int force_recheck;  // filter mode: decide every pair in float64
+  int count_cap;      // MarkCore counts neighbours up to this value (largest minPts of the eps)
   double E2;
   double side;
   const double* pts;  // input, [n][D]
@@ -65,6 +66,7 @@ struct Work {
   int32_t* cellMin;   // [n] per cell: smallest input index of its core points
   int32_t* nroot[kTreeLevels + 1];  // per tree node (levels 1..): common root or -1/-2
   int32_t* blabel;    // [n] border label, cell order
+  int32_t* cnt;       // [n] neighbours within eps, capped at count_cap, cell order
 };
 
 constexpr int kBBoxBlocks = 512;
@@ -76,21 +78,25 @@ DB_DEV uint32_t epoch_of(const GridDesc* desc, uint32_t slot) {
 // ---------------------------------------------------------------------------
 // Call initialisation: counters, histograms and the epoch.
 // ---------------------------------------------------------------------------
-__global__ void k_init(Work W) {
+// `first`: the first grid of a call (or of a batch) also clears the status and the
+// cumulative counters.
+__global__ void k_init(Work W, int first) {
   const int t = threadIdx.x;
   for (int i = t; i < 8 * 256; i += blockDim.x) W.ghist[i] = 0;
   if (t < 16) W.tilectr[t] = 0;
   if (t == 0) {
     GridDesc* g = W.desc;
     g->epoch = g->epoch + 1;
-    g->status = 0;
     g->n_cells = 0;
     g->n_unsafe = 0;
     g->n_core = 0;
     g->max_extent_bits = 0;
-    g->bcp_calls = 0;
-    g->uf_links = 0;
-    g->rechecks = 0;
+    if (first) {
+      g->status = 0;
+      g->bcp_calls = 0;
+      g->uf_links = 0;
+      g->rechecks = 0;
+    }
   }
 }
 
@@ -626,7 +632,7 @@ __global__ void k_thresholds(Work W, double eps) {
   double tin = ain > 0.0 ? (1.0 - gd) * ain * ain * (1.0 - 0x1p-40) : -1.0;
   double tout = (1.0 + gd) * aout * aout * (1.0 + 0x1p-40);
   const bool ok = E2 >= 0x1p-100 && E2 <= 0x1p100 && (eps + 2.0 * M) <= 0x1p60 &&
-                  __builtin_isfinite(tout) && g->status == 0;
+                  __builtin_isfinite(tout) && (g->status & 1u) == 0;
   if (!ok || W.force_recheck) {
     tin = -__builtin_inf();
     tout = __builtin_inf();

@@ -1,0 +1,123 @@
+"""Batches of clouds and settings (one captured HIP graph) against the oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import dbscan_o1
+from tests.gpu_helpers import gpu_dbscan, log
+from workloads import gaussian_mixture, multi_cloud_batch, seed_spreader_3d
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(clouds, settings, mode):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    return binding.Batch([torch.from_numpy(X).to("cuda") for X in clouds], settings, mode=mode)
+
+
+def _check_batch(b, clouds, settings, tag):
+    for i, (X, st) in enumerate(zip(clouds, settings)):
+        for s, (eps, mp) in enumerate(st):
+            want = dbscan_o1(X, eps, mp)
+            core = b.core[i][s].cpu().numpy()
+            lab = b.label[i][s].cpu().numpy()
+            assert np.array_equal(core, want[0]), f"{tag}: cloud {i} setting {s} core"
+            assert np.array_equal(lab, want[1]), f"{tag}: cloud {i} setting {s} labels"
+
+
+def _clouds():
+    rng = np.random.Generator(np.random.PCG64(401))
+    n = 30_000
+    A = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=402)
+    B = gaussian_mixture(5000, 2, 8, 0.5, 10.0, 0.05, rng)
+    C = gaussian_mixture(4000, 5, 6, 1.0, 10.0, 0.05, rng)
+    E = np.zeros((0, 3))
+    settings = [
+        [(200.0, 5), (200.0, 10), (400.0, 50), (200.0, 100), (400.0, 5)],
+        [(0.3, 4)],
+        [(1.5, 10), (2.0, 10)],
+        [(1.0, 3)],
+    ]
+    return [A, B, C, E], settings
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
+def test_batch_matches_oracle(mode, gpu_lib):
+    clouds, settings = _clouds()
+    b = _batch(clouds, settings, mode)
+    log(f"batch mode={mode} clouds={len(clouds)}")
+    b.run()
+    _check_batch(b, clouds, settings, f"batch {mode}")
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
+def test_graph_replays_match_eager(mode, gpu_lib):
+    """Replay the captured graph several times with eager work between replays;
+    every replay must equal the eager (uncaptured) batch."""
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    clouds, settings = _clouds()
+    b = _batch(clouds, settings, mode)
+    binding.set_option("batch_graph", 0)
+    try:
+        log(f"eager batch mode={mode}")
+        b.run()
+        ref = [(c.clone(), l.clone()) for c, l in zip(b.core, b.label)]
+    finally:
+        binding.set_option("batch_graph", 1)
+    rng = np.random.default_rng(5)
+    for r in range(4):
+        for c, l in zip(b.core, b.label):
+            c.fill_(7)
+            l.fill_(-7)
+        log(f"graph replay {r} mode={mode}")
+        b.run()
+        for (c, l), (rc, rl) in zip(zip(b.core, b.label), ref):
+            assert torch.equal(c, rc) and torch.equal(l, rl), f"replay {r} differs"
+        # eager work on the same context between replays
+        Y = rng.uniform(0, 10, (3000, 2))
+        got = gpu_dbscan(Y, 0.4, 5, mode=mode, tag=f"eager between replays {r}")
+        want = dbscan_o1(Y, 0.4, 5)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+        torch.cuda.synchronize()
+
+
+def test_batch_recaptures_when_description_changes(gpu_lib):
+    clouds, settings = _clouds()
+    b1 = _batch(clouds[:2], settings[:2], "fp32_filter")
+    b2 = _batch(clouds[2:], settings[2:], "fp32_filter")
+    for r in range(2):
+        log(f"alternate batches {r}")
+        b1.run()
+        _check_batch(b1, clouds[:2], settings[:2], "b1")
+        b2.run()
+        _check_batch(b2, clouds[2:], settings[2:], "b2")
+
+
+def test_multi_cloud_batch_small(gpu_lib):
+    inst = multi_cloud_batch(n_clouds=40, size_scale=0.01)
+    clouds = [i.X for i in inst]
+    settings = [list(zip(i.eps, i.min_pts)) for i in inst]
+    b = _batch(clouds, settings, "fp32_filter")
+    log("multi-cloud batch 40 clouds")
+    b.run()
+    b.run()
+    _check_batch(b, clouds, settings, "multi-cloud")
+
+
+def test_batch_invalid_arguments(gpu_lib):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    X = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+    for st in ([(0.0, 3)], [(1.0, 0)], [(float("nan"), 2)]):
+        b = binding.Batch([X], [st], mode="fp64")
+        with pytest.raises(binding.DbscanError) as e:
+            b.run()
+        assert e.value.code == binding.EINVAL
