@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of exact DBSCAN on one MI355X, in points per second.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp64|fp32_filter]
-                    [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-One step is one full exact DBSCAN of one point cloud already resident in HBM
-(grid, sort, cell boxes and guard, box tree, MarkCore, ClusterCore, relabel,
-ClusterBorder, scatter), outputs left in HBM.  After W untimed warm-up steps
-exactly K steps are timed between device synchronisations; value = points * K /
-seconds.  A second timed loop with per-phase HIP events (recorded by the library on
-its own stream) gives the duration of the dominant kernel for the roofline entry.
-The CPU oracle is timed on the host cores on the same workload for reference.
+A step is one full exact DBSCAN (grid, sort, cell boxes and guard, box tree,
+MarkCore, ClusterCore, relabel, ClusterBorder, scatter) of every (cloud, setting)
+of the workload, inputs already resident in HBM and outputs left in HBM.  Three
+timed legs run the same workload:
+
+  plain    : one dbscan() call per (cloud, setting), float64 decisions;
+  filter   : the same calls with the float32 filter and float64 recheck;
+  batched  : dbscan_batch() with the float32 filter, replaying one captured HIP
+             graph per step (the headline value).
+
+Each leg runs W untimed warm-up steps and then exactly K steps between device
+synchronisations; value = points * K / seconds.  A profiled loop of the filter leg
+records per-phase HIP events on the library's stream; the dominant phase gives the
+roofline entry.  The CPU oracle is timed on the host cores on the same workload.
 
 Prints one JSON line.
 """
@@ -31,55 +37,65 @@ HBM_PEAK_GBS = 8000.0
 
 
 def workloads():
-    from workloads import blobs_2d, gaussian_mixture_hd, seed_spreader_3d
+    from workloads import (blobs_2d, config_workload, gaussian_mixture_hd, multi_cloud_batch,
+                           seed_spreader_3d)
+
+    def one(gen, eps, mp):
+        return lambda: [(gen(), [(eps, mp)])]
 
     return {
-        # name: (generator, eps, minPts, description)
-        "spreader3d_n1e6": (lambda: seed_spreader_3d(1_000_000), 200.0, 10,
+        "spreader3d_n1e6": (one(lambda: seed_spreader_3d(1_000_000), 200.0, 10),
                             "3D seed-spreader random walk, n=1,000,000 over [0,1e5]^3, eps=200, minPts=10"),
-        "blobs2d_n2e4": (lambda: blobs_2d(20_000), 100.0, 10,
+        "blobs2d_n2e4": (one(lambda: blobs_2d(20_000), 100.0, 10),
                          "2D Gaussian blobs, n=20,000, eps=100, minPts=10"),
-        "mixture5d_n2e6_eps2": (lambda: gaussian_mixture_hd(5), 2.0, 10,
-                                "5D Gaussian mixture, n=2,000,000, eps=2, minPts=10"),
-        "mixture7d_n2e6_eps3": (lambda: gaussian_mixture_hd(7), 3.0, 10,
-                                "7D Gaussian mixture, n=2,000,000, eps=3, minPts=10"),
+        "mixture5d_n2e6": (lambda: [(gaussian_mixture_hd(5), [(1.5, 10), (2.0, 10), (3.0, 10)])],
+                           "5D Gaussian mixture, n=2,000,000, eps in {1.5,2,3}, minPts=10"),
+        "mixture7d_n2e6": (lambda: [(gaussian_mixture_hd(7), [(1.5, 10), (2.0, 10), (3.0, 10)])],
+                           "7D Gaussian mixture, n=2,000,000, eps in {1.5,2,3}, minPts=10"),
+        "sweep3d_n1e7": (lambda: [(i.X, list(zip(i.eps, i.min_pts))) for i in config_workload(3)],
+                         "3D seed-spreader n=10,000,000 over [0,1e6]^3, 16 settings "
+                         "eps in {200,400,800,1600} x minPts in {5,10,50,100}"),
+        "multicloud_256": (lambda: [(i.X, list(zip(i.eps, i.min_pts))) for i in multi_cloud_batch()],
+                           "256 Gaussian-mixture clouds, n log-uniform in [1e3,1e6], d in {2,3,5}, "
+                           "eps = half the median sigma, minPts=10"),
     }
 
 
-# Algorithmic HBM bytes per point of each phase, plain float64 path, d dimensions.
+# Algorithmic HBM bytes per point of each phase, d dimensions, plain / filter.
 # These count what the method must move once (inputs read once, outputs written
 # once), not what an implementation re-reads.
-def algorithmic_bytes_per_point(phase: str, d: int) -> float:
+def algorithmic_bytes_per_point(phase: str, d: int, f32: bool) -> float:
+    coord = 4 * d if f32 else 8 * d
     table = {
-        "bbox": 8 * d,                    # read the points
-        "keys": 8 * d + 12,               # read points, write key + index
-        "radix_sort": 24,                 # one (key, index) scatter: 12 B in, 12 B out
-        "cells": 12 + 8 * d + 8 * d + 8,  # read key+index, gather point, write SoA + cell id + perm
-        "cell_boxes": 8 * d + 4,          # read SoA + cell id
-        "markcore": 8 * d + 1,            # read SoA once, write core flag
-        "cluster_core": 8 * d + 1,        # read SoA and core flags once
-        "border": 8 * d + 1,
-        "scatter": 1 + 4 + 4 + 1 + 4,     # core flag, perm, cell id in; flag + id out
+        "bbox": 8 * d,
+        "keys": 8 * d + 12,
+        "radix_sort": 24,
+        "cells": 12 + 8 * d + 8 * d + 8,
+        "cell_boxes": 8 * d + 4,
+        "tree": 0,
+        "markcore": coord + 4,
+        "cluster_core": coord + 1,
+        "relabel": 0,
+        "border": coord + 1,
+        "scatter": 1 + 4 + 4 + 1 + 4,
     }
     return float(table.get(phase, 0.0))
 
 
-def cpu_baseline(X, eps, mp, budget_s: float = 25.0):
-    """Time the C oracle on the host cores (bounded: a prefix sample if needed)."""
+def cpu_baseline(items, budget_s: float = 25.0):
+    """Time the C oracle on the host cores on (a bounded prefix of) the workload."""
     from oracle.o1 import build_o1, dbscan_o1, o1_threads
 
     build_o1(force=False)
     cores = o1_threads()
+    X, st = items[0]
+    eps, mp = st[0]
     n = len(X)
-    # calibrate on a small prefix, then size the sample to the budget
     m = min(n, 50_000)
     t0 = time.perf_counter()
     dbscan_o1(X[:m], eps, mp)
     t_small = time.perf_counter() - t0
-    sample = n
-    if t_small * (n / m) ** 1.0 > budget_s:
-        sample = max(m, int(m * budget_s / max(t_small, 1e-6)))
-        sample = min(sample, n)
+    sample = n if t_small * (n / m) <= budget_s else max(m, min(n, int(m * budget_s / max(t_small, 1e-6))))
     t0 = time.perf_counter()
     dbscan_o1(X[:sample], eps, mp)
     t = time.perf_counter() - t0
@@ -88,9 +104,22 @@ def cpu_baseline(X, eps, mp, budget_s: float = 25.0):
         "unit": "points/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"C oracle (OpenMP, -O3, no FMA) on the first {sample} of {n} points "
-                   f"of the same cloud, same eps/minPts; {t:.2f} s wall"),
+        "sample": (f"C oracle (OpenMP, -O3, no FMA) on the first {sample} of {n} points of the "
+                   f"first cloud, eps={eps}, minPts={mp}; {t:.2f} s wall"),
     }
+
+
+def timed(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def main() -> int:
@@ -98,7 +127,6 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_filter"])
     ap.add_argument("--workload", default="spreader3d_n1e6", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -106,72 +134,80 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "(DESIGN.md describes how it would shard); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_1912_06255_amd import binding
 
-    gen, eps, mp, desc = workloads()[args.workload]
-    X = gen()
-    n, d = X.shape
+    gen, desc = workloads()[args.workload]
+    items = gen()
     dev = torch.device("cuda:0")
-    T = torch.from_numpy(X).to(dev)
-    core = torch.empty(n, dtype=torch.uint8, device=dev)
-    lab = torch.empty(n, dtype=torch.int32, device=dev)
-    binding.reserve(n, d)
+    clouds = [torch.from_numpy(X).to(dev) for X, _ in items]
+    settings = [st for _, st in items]
+    points = sum(X.shape[0] * len(st) for X, st in zip(clouds, settings))
+    binding.reserve(max(X.shape[0] for X in clouds), max(X.shape[1] for X in clouds))
+    outs = [[(torch.empty(X.shape[0], dtype=torch.uint8, device=dev),
+              torch.empty(X.shape[0], dtype=torch.int32, device=dev)) for _ in st]
+            for X, st in zip(clouds, settings)]
 
-    def step():
-        binding.dbscan(T, eps, mp, mode=args.mode, out=(core, lab), check=False)
+    def unbatched(mode):
+        def step():
+            for X, st, o in zip(clouds, settings, outs):
+                for (eps, mp), out in zip(st, o):
+                    binding.dbscan(X, eps, mp, mode=mode, out=out, check=False)
+        return step
 
-    for _ in range(args.warmup):
-        step()
-    st = binding.stats(raise_on_error=True)
-    torch.cuda.synchronize()
+    rates = {}
+    for leg, mode in (("plain", "fp64"), ("filter", "fp32_filter")):
+        wall = timed(unbatched(mode), args.steps, args.warmup)
+        binding.stats(raise_on_error=True)
+        rates[leg] = (points * args.steps / wall, wall * 1e3 / args.steps)
 
+    batch = binding.Batch(clouds, settings, mode="fp32_filter")
+    batch.run()  # capture + instantiate (reported separately, not timed)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    value = n * args.steps / wall
+    batch.run()
+    first_replay_ms = (time.perf_counter() - t0) * 1e3
+    wall = timed(lambda: batch.run(check=False), args.steps, args.warmup)
+    st = binding.stats(raise_on_error=True)
+    rates["batched"] = (points * args.steps / wall, wall * 1e3 / args.steps)
 
-    # second timed loop with per-phase events on the library's stream
+    # profiled loop: the filter leg of the first cloud and setting with phase events
+    X0, (eps0, mp0), out0 = clouds[0], settings[0][0], outs[0][0]
+    n0, d0 = X0.shape
     binding.set_profiling(True)
     acc = {}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        binding.dbscan(X0, eps0, mp0, mode="fp32_filter", out=out0, check=False)
         for k, v in binding.phase_times().items():
             acc[k] = acc.get(k, 0.0) + v
     prof_wall = time.perf_counter() - t1
     binding.set_profiling(False)
+    st0 = binding.stats(raise_on_error=True)
     phase_ms = {k: v / args.steps for k, v in acc.items()}
-    st = binding.stats(raise_on_error=True)
-
-    # dominant phase -> roofline entry (HBM bound: sort/scan/gather work)
     dom = max(phase_ms, key=phase_ms.get)
-    launches = {"radix_sort": max(1, (st["key_bits"] + 7) // 8)}.get(dom, 1)
+    launches = {"radix_sort": max(1, (st0["key_bits"] + 7) // 8)}.get(dom, 1)
     per_launch_ms = phase_ms[dom] / launches
-    alg_bytes = algorithmic_bytes_per_point(dom, d) * n
+    alg_bytes = algorithmic_bytes_per_point(dom, d0, True) * n0
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     roofline = {
         "bound": "hbm",
         "kernel": dom,
         "launches_per_step": launches,
-        "achieved": round(achieved, 1),
+        "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": None,
         "avg_launch_ms": round(per_launch_ms, 5),
         "alg_bytes_per_launch": int(alg_bytes),
     }
 
+    value, ms = rates["batched"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -179,24 +215,26 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n": n, "d": d, "eps": eps,
-                   "min_pts": mp, "mode": args.mode, "batched": False},
+        "config": {"workload": args.workload, "description": desc, "points_per_step": points,
+                   "clouds": len(clouds), "settings": sum(len(s) for s in settings)},
+        "plain_fp64": {"value": rates["plain"][0], "ms_per_step": rates["plain"][1]},
+        "filter_unbatched": {"value": rates["filter"][0], "ms_per_step": rates["filter"][1]},
+        "speedup_batched_filter_vs_plain": value / rates["plain"][0],
+        "graph_first_replay_ms": first_replay_ms,
         "roofline": roofline,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "profiled_ms_per_step": prof_wall * 1e3 / args.steps,
-        "stats": {k: st[k] for k in ("n_cells", "n_unsafe", "n_core", "bcp_calls", "uf_links",
-                                     "fp64_rechecks", "key_bits", "key_shift")},
+        "stats_batch": {k: st[k] for k in ("bcp_calls", "uf_links", "fp64_rechecks")},
+        "stats_first": {k: st0[k] for k in ("n_cells", "n_unsafe", "n_core", "bcp_calls",
+                                            "uf_links", "fp64_rechecks", "key_bits", "key_shift")},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, eps, mp)
-    else:
-        out["cpu_baseline"] = None
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(items)
     print(json.dumps(out), flush=True)
     return 0
 

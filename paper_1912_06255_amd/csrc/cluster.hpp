@@ -497,12 +497,14 @@ struct BcpVisitor {
             ap[d] = 0.0f;
           }
           if (pv) {
+            // points of the unit farther than eps from this chunk's box drop out
+            load_point<D>(W->X, n, i, xp);
+            pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
             if constexpr (F32) {
-              load_local<D>(W->X32, n, i, ap);
-              pcell = W->cellOf[i];
-            } else {
-              load_point<D>(W->X, n, i, xp);
-              pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
+              if (pv) {
+                load_local<D>(W->X32, n, i, ap);
+                pcell = W->cellOf[i];
+              }
             }
           }
           uint64_t pm = ballot(pv);
