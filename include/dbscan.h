@@ -72,6 +72,7 @@ typedef struct {
   int64_t bcp_calls;     /* cell pairs that reached a closest-pair test */
   int64_t uf_links;      /* successful union-find links */
   int64_t fp64_rechecks; /* pairs re-decided in float64 (FP32 filter mode) */
+  int64_t pair_tests;    /* point-pair distance decisions made by ClusterCore */
   int32_t key_bits;      /* bits of the Morton cell key */
   int32_t key_shift;     /* key coordinate = floor(cell index / 2^key_shift) */
   uint32_t status;       /* 0 or a bit set of DBSCAN_STATUS_* */

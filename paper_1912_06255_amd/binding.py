@@ -45,6 +45,7 @@ class Stats(ctypes.Structure):
         ("bcp_calls", ctypes.c_int64),
         ("uf_links", ctypes.c_int64),
         ("fp64_rechecks", ctypes.c_int64),
+        ("pair_tests", ctypes.c_int64),
         ("key_bits", ctypes.c_int32),
         ("key_shift", ctypes.c_int32),
         ("status", ctypes.c_uint32),

@@ -224,16 +224,30 @@ DB_DEV bool recheck64(const Work* W, int pi, int qi) {
 // lane.  Returns whether q is within eps of p; band lanes are rechecked.
 template <int D>
 DB_DEV bool filtered_hit(const Work* W, bool valid, const float (&ap)[D], const float (&aq)[D],
-                         const float (&off)[D], float tin, float tout, int pi, int qi) {
+                         const float (&off)[D], float tin, float tout, int pi, int qi,
+                         unsigned long long& rechecks) {
   const int cls = valid ? decide32<D>(ap, aq, off, tin, tout) : 0;
   bool hit = cls == 1;
   const uint64_t bm = ballot(cls == 2);
   if (bm) {
     if (cls == 2) hit = recheck64<D>(W, pi, qi);
-    if (lane_id() == 0) atomicAdd(&W->desc->rechecks, (unsigned long long)__popcll(bm));
+    rechecks += (unsigned long long)__popcll(bm);
   }
   return hit;
 }
+
+// Per-wave counters of one unit of work, flushed once with stat_add.
+struct Counters {
+  unsigned long long bcp = 0, links = 0, rechecks = 0, pairs = 0;
+  DB_DEV void flush(GridDesc* g) const {
+    if (lane_id() == 0) {
+      stat_add(g, kCtrBcp, bcp);
+      stat_add(g, kCtrLinks, links);
+      stat_add(g, kCtrRechecks, rechecks);
+      stat_add(g, kCtrPairs, pairs);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // MarkCore (Algorithm 2).  A cell with at least minPts points is all core (its
@@ -255,6 +269,7 @@ struct MarkCoreVisitor {
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
   double ag[D];      // anchor of g (filter mode)
   float tin, tout;
+  Counters ctr;
 
   DB_DEV bool group(int cb, uint64_t m) {
     if (g >= cb && g < cb + 64) m &= ~(1ull << (g - cb));
@@ -292,7 +307,7 @@ struct MarkCoreVisitor {
           float at[D];
 #pragma unroll
           for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q);
+          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks);
         } else {
           double xp[D];
 #pragma unroll
@@ -353,6 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk<D>(W.tree, C, q, v);
       if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
+      v.ctr.flush(W.desc);
     }
   }
 }
@@ -385,11 +401,11 @@ __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
     }
     ncore += cc;
   }
-  if (lane == 0 && ncore) atomicAdd(&W.desc->n_core, ncore);
+  if (lane == 0) stat_add(W.desc, kCtrCore, (unsigned long long)ncore);
 }
 
 __global__ void k_setting_init(Work W) {
-  if (threadIdx.x == 0) W.desc->n_core = 0;
+  if (threadIdx.x < kCtrSlots) W.desc->ctr[kCtrCore][threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -415,6 +431,7 @@ struct BcpVisitor {
   int excl_level;  // node already covered by an earlier round (level, index), or -1
   int excl_idx;
   bool prune;      // node roots of the previous round are valid
+  Counters ctr;
 
   // A node is skipped when an earlier round already handled it, when it has no
   // core cell, or when all its core cells were in one component that the unit has
@@ -441,7 +458,7 @@ struct BcpVisitor {
     }
     uint64_t alive = ballot(on);
     if (!alive) return false;
-    if (lane == 0) atomicAdd(&W->desc->bcp_calls, (unsigned long long)__popcll(alive));
+    ctr.bcp += (unsigned long long)__popcll(alive);
     const int c0 = ps >> 6;
     const int nchk = ((pe - 1) >> 6) - c0 + 1;
     const int tot = flatten(F, W->cellStart, cb, alive);
@@ -516,6 +533,7 @@ struct BcpVisitor {
             const int t = __ffsll((long long)pm) - 1;
             pm &= pm - 1;
             bool hit;
+            ctr.pairs += (unsigned long long)__popcll(ballot(valid));
             if constexpr (F32) {
               const int pc = bcast(pcell, t);
               if (pc != curcell) {
@@ -527,7 +545,8 @@ struct BcpVisitor {
               float at[D];
 #pragma unroll
               for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-              hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q);
+              hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
+                                    ctr.rechecks);
             } else {
               double xt[D];
 #pragma unroll
@@ -541,8 +560,9 @@ struct BcpVisitor {
               cells &= cells - 1;
               if (!((alive >> c) & 1ull)) continue;
               const int rc = bcast(hr, c);
-              if (lane == 0 && uf_link(W->parent, ucell, cb + c))
-                atomicAdd(&W->desc->uf_links, 1ull);
+              bool linked = false;
+              if (lane == 0) linked = uf_link(W->parent, ucell, cb + c);
+              ctr.links += ballot(linked) ? 1ull : 0ull;
               alive &= ~ballot(hr == rc);  // that whole component has joined
             }
             valid = valid && ((alive >> j) & 1ull);
@@ -619,6 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
     const int anc_level = round < 0 ? top + 1 : round + 1;
     const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
     walk_subtree<D>(W.tree, cnt, anc_level, anc, v.uq, v);
+    v.ctr.flush(W.desc);
   }
 }
 
@@ -703,6 +724,7 @@ struct BorderVisitor {
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
   double ag[D];      // anchor of g (filter mode)
   float tin, tout;
+  Counters ctr;
 
   DB_DEV bool group(int cb, uint64_t m) {
     const int lane = lane_id();
@@ -751,7 +773,7 @@ struct BorderVisitor {
           float at[D];
 #pragma unroll
           for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-          hit = filtered_hit<D>(W, cand, at, aq, off, tin, tout, bcast(pidx, t), q);
+          hit = filtered_hit<D>(W, cand, at, aq, off, tin, tout, bcast(pidx, t), q, ctr.rechecks);
         } else {
           double xp[D];
 #pragma unroll
@@ -827,6 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk<D>(W.tree, C, q, v);
       if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
+      v.ctr.flush(W.desc);
     }
   }
 }

@@ -29,13 +29,19 @@ struct GridDesc {
   uint32_t status;        // DBSCAN_STATUS_* bits
   int32_t n_cells;        // C before/after splitting
   int32_t n_unsafe;       // cells whose float64 diameter test failed
-  int32_t n_core;
   unsigned long long max_extent_bits;  // largest cell extent (float64 bits, >= 0)
   float tin, tout;        // float32 filter thresholds (IN if <= tin, OUT if > tout)
-  unsigned long long bcp_calls;
-  unsigned long long uf_links;
-  unsigned long long rechecks;
+  // Counters, spread over kCtrSlots addresses (by wave) so that concurrent
+  // updates do not serialise on one address; the host sums the slots.
+  unsigned long long ctr[5][64];
 };
+
+constexpr int kCtrSlots = 64;
+enum { kCtrBcp = 0, kCtrLinks = 1, kCtrRechecks = 2, kCtrPairs = 3, kCtrCore = 4 };
+
+DB_DEV void stat_add(GridDesc* g, int which, unsigned long long v) {
+  if (v) atomicAdd(&g->ctr[which][(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCtrSlots - 1)], v);
+}
 
 // ---------------------------------------------------------------------------
 // Wave helpers

@@ -509,10 +509,14 @@ int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
   out->n_points = ctx->last_n;
   out->n_cells = g.n_cells;
   out->n_unsafe = g.n_unsafe;
-  out->n_core = g.n_core;
-  out->bcp_calls = (int64_t)g.bcp_calls;
-  out->uf_links = (int64_t)g.uf_links;
-  out->fp64_rechecks = (int64_t)g.rechecks;
+  int64_t sum[5] = {0, 0, 0, 0, 0};
+  for (int w = 0; w < 5; ++w)
+    for (int i = 0; i < kCtrSlots; ++i) sum[w] += (int64_t)g.ctr[w][i];
+  out->n_core = sum[kCtrCore];
+  out->bcp_calls = sum[kCtrBcp];
+  out->uf_links = sum[kCtrLinks];
+  out->fp64_rechecks = sum[kCtrRechecks];
+  out->pair_tests = sum[kCtrPairs];
   out->key_bits = g.total_bits;
   out->key_shift = g.shift;
   out->status = g.status;

@@ -84,19 +84,17 @@ __global__ void k_init(Work W, int first) {
   const int t = threadIdx.x;
   for (int i = t; i < 8 * 256; i += blockDim.x) W.ghist[i] = 0;
   if (t < 16) W.tilectr[t] = 0;
+  GridDesc* g = W.desc;
+  for (int i = t; i < 5 * kCtrSlots; i += blockDim.x) {
+    const int which = i / kCtrSlots;
+    if (first || which == kCtrCore) g->ctr[which][i % kCtrSlots] = 0;
+  }
   if (t == 0) {
-    GridDesc* g = W.desc;
     g->epoch = g->epoch + 1;
     g->n_cells = 0;
     g->n_unsafe = 0;
-    g->n_core = 0;
     g->max_extent_bits = 0;
-    if (first) {
-      g->status = 0;
-      g->bcp_calls = 0;
-      g->uf_links = 0;
-      g->rechecks = 0;
-    }
+    if (first) g->status = 0;
   }
 }
 

@@ -53,5 +53,5 @@ def test_null_arguments_are_rejected_without_touching_a_gpu(lib):
 
 
 def test_stats_struct_matches_header():
-    # int64 x7 + int32 x2 + uint32 x2
-    assert ctypes.sizeof(binding.Stats) == 7 * 8 + 4 * 4
+    # int64 x8 + int32 x2 + uint32 x2
+    assert ctypes.sizeof(binding.Stats) == 8 * 8 + 4 * 4
