@@ -129,6 +129,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="spreader3d_n1e6", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only run the workload a few times in each mode plus a reference "
+                         "elementwise kernel of known size (256 MiB read, 256 MiB written), "
+                         "for rocprofv3 counter runs; prints no JSON")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,6 +162,19 @@ def main() -> int:
                 for (eps, mp), out in zip(st, o):
                     binding.dbscan(X, eps, mp, mode=mode, out=out, check=False)
         return step
+
+    if args.profile_pass:
+        for mode in ("fp64", "fp32_filter"):
+            for _ in range(3):
+                unbatched(mode)()
+        binding.stats(raise_on_error=True)
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 2.0, out=b)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        print("profile pass done", flush=True)
+        return 0
 
     rates = {}
     for leg, mode in (("plain", "fp64"), ("filter", "fp32_filter")):

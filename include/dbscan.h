@@ -180,6 +180,8 @@ const char *dbscan_phase_name(int32_t phase);
  *                          float64 recheck (for testing; default 0)
  *   DBSCAN_OPT_BATCH_GRAPH 1: dbscan_batch() captures and replays a HIP graph
  *                          (default); 0: it launches its kernels directly
+ *   DBSCAN_OPT_BCP_SPLIT   waves per ClusterCore unit, each taking every k-th
+ *                          neighbour group of the unit (1..64, default 1)
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -187,6 +189,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_FINE_BITS 3
 #define DBSCAN_OPT_FORCE_RECHECK 4
 #define DBSCAN_OPT_BATCH_GRAPH 5
+#define DBSCAN_OPT_BCP_SPLIT 6
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

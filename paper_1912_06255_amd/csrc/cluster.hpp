@@ -10,6 +10,9 @@ namespace db {
 
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kNodeNoCore = -2;
+// Mean points per live neighbour cell from which ClusterCore handles a group cell
+// by cell instead of flattening it.
+constexpr int kDenseGroup = 24;
 
 // ---------------------------------------------------------------------------
 // Tree walk.  Every node whose box can hold a point within eps of the query box
@@ -28,41 +31,86 @@ struct Query {
 //   static constexpr bool kNearestFirst  enter child nodes by increasing box distance
 //   bool keep_node(int level, int idx)   false drops a node (level >= 1) unvisited
 //   bool group(int first_cell, uint64_t mask)
-template <int D, int L, class V>
-DB_DEV bool visit_node(const TreeView& T, const int (&cnt)[kTreeLevels + 2], int node,
-                       const Query<D>& q, V& vis) {
-  const int cb = node * 64;
-  const int ch = cb + lane_id();
-  double dist = __builtin_inf();
-  if (ch < cnt[L - 1]) {
+//
+// The walk is iterative: one frame per tree level (the mask of children still to
+// enter, their first index and, for nearest-first walks, their box distances) is
+// kept in a per-wave LDS stack, so that the visitor's group() is expanded once.
+struct WalkStack {
+  uint64_t* m;   // [kTreeLevels + 2]
+  int* cb;       // [kTreeLevels + 2]
+  double* dist;  // [(kTreeLevels + 2) * 64], nearest-first walks only
+};
+
+// Number of nodes at level l for C cells (level 0 = cells).
+DB_DEV int nodes_at(int C, int l) {
+  return (int)(((long long)C + (1ll << (6 * l)) - 1) >> (6 * l));
+}
+
+// Children (at level L - 1) of node N at level L that can hold a point within eps
+// of the query box.  dist: this lane's child box distance, +inf if dropped.
+template <int D, class V>
+DB_DEV uint64_t test_children(const TreeView& T, int C, int L, int N, const Query<D>& q, V& vis,
+                              double& dist) {
+  const int ch = N * 64 + lane_id();
+  dist = __builtin_inf();
+  if (ch < nodes_at(C, L - 1)) {
     const double bd = box_sqdist<D>(q.lo, q.hi, T.lo[L - 1], T.hi[L - 1], T.cap[L - 1], ch);
     if (bd <= q.E2) dist = bd;
   }
   bool ok = dist <= q.E2;
-  if constexpr (L >= 2) {
-    if (ok) ok = vis.keep_node(L - 1, ch);
+  if (L >= 2 && ok) ok = vis.keep_node(L - 1, ch);
+  if (!ok) dist = __builtin_inf();
+  return ballot(ok);
+}
+
+// Walk the subtree of node `node` at level `level` (1 .. top + 1).
+template <int D, class V>
+DB_DEV void walk_subtree(const TreeView& T, int C, int level, int node, const Query<D>& q, V& vis,
+                         const WalkStack& S) {
+  const int lane = lane_id();
+  double dist;
+  const uint64_t m0 = test_children<D>(T, C, level, node, q, vis, dist);
+  if (level == 1) {
+    if (m0) vis.group(node * 64, m0);
+    return;
   }
-  uint64_t m = ballot(ok);
-  if constexpr (L == 1) {
-    return m ? vis.group(cb, m) : false;
-  } else {
-    if constexpr (V::kNearestFirst) {
-      if (!ok) dist = __builtin_inf();
-      while (m) {
-        const double mind = wave_min(dist);
-        const int j = __ffsll((long long)(ballot(dist == mind) & m)) - 1;
-        m &= ~(1ull << j);
-        if (lane_id() == j) dist = __builtin_inf();
-        if (visit_node<D, L - 1, V>(T, cnt, cb + j, q, vis)) return true;
-      }
-    } else {
-      while (m) {
-        const int j = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        if (visit_node<D, L - 1, V>(T, cnt, cb + j, q, vis)) return true;
-      }
+  int lvl = level;
+  wave_sync();
+  S.m[lvl] = m0;
+  S.cb[lvl] = node * 64;
+  if constexpr (V::kNearestFirst) S.dist[lvl * 64 + lane] = dist;
+  wave_sync();
+  while (true) {
+    const uint64_t fm = S.m[lvl];
+    if (!fm) {
+      if (++lvl > level) break;
+      continue;
     }
-    return false;
+    int j;
+    if constexpr (V::kNearestFirst) {
+      const double dv = ((fm >> lane) & 1ull) ? S.dist[lvl * 64 + lane] : __builtin_inf();
+      const double mind = wave_min(dv);
+      j = __ffsll((long long)(ballot(dv == mind) & fm)) - 1;
+    } else {
+      j = __ffsll((long long)fm) - 1;
+    }
+    const int child = S.cb[lvl] + j;  // a node at level lvl - 1
+    wave_sync();
+    S.m[lvl] = fm & ~(1ull << j);
+    wave_sync();
+    double d2;
+    const uint64_t m2 = test_children<D>(T, C, lvl - 1, child, q, vis, d2);
+    if (!m2) continue;
+    if (lvl - 1 == 1) {
+      if (vis.group(child * 64, m2)) return;
+    } else {
+      --lvl;
+      wave_sync();
+      S.m[lvl] = m2;
+      S.cb[lvl] = child * 64;
+      if constexpr (V::kNearestFirst) S.dist[lvl * 64 + lane] = d2;
+      wave_sync();
+    }
   }
 }
 
@@ -80,29 +128,13 @@ DB_DEV int top_level(const int (&cnt)[kTreeLevels + 2]) {
   return top;
 }
 
-// Walk the subtree of node `node` at level `level` (1 .. top + 1).
 template <int D, class V>
-DB_DEV void walk_subtree(const TreeView& T, const int (&cnt)[kTreeLevels + 2], int level, int node,
-                         const Query<D>& q, V& vis) {
-  switch (level) {
-    case 1: visit_node<D, 1, V>(T, cnt, node, q, vis); break;
-    case 2: visit_node<D, 2, V>(T, cnt, node, q, vis); break;
-    case 3: visit_node<D, 3, V>(T, cnt, node, q, vis); break;
-    case 4: visit_node<D, 4, V>(T, cnt, node, q, vis); break;
-    case 5: visit_node<D, 5, V>(T, cnt, node, q, vis); break;
-    default: visit_node<D, 6, V>(T, cnt, node, q, vis); break;
-  }
-}
-
-template <int D, class V>
-DB_DEV void walk(const TreeView& T, int C, const Query<D>& q, V& vis) {
+DB_DEV void walk(const TreeView& T, int C, const Query<D>& q, V& vis, const WalkStack& S) {
   int cnt[kTreeLevels + 2];
   level_counts(C, cnt);
-  walk_subtree<D, V>(T, cnt, top_level(cnt) + 1, 0, q, vis);
+  walk_subtree<D, V>(T, C, top_level(cnt) + 1, 0, q, vis, S);
 }
 
-// The tree has kTreeLevels node levels; visit_node<.., 6> reads level 5 boxes.
-static_assert(kTreeLevels == 5, "walk() dispatch assumes five node levels");
 
 // ---------------------------------------------------------------------------
 // Flattening the points of the masked cells of a 64-cell group so that the 64
@@ -122,6 +154,18 @@ DB_DEV int flatten(const Flat& F, const int32_t* cellStart, int cb, uint64_t m) 
     s = cellStart[cb + lane];
     cnt = cellStart[cb + lane + 1] - s;
   }
+  const int incl = wave_incl_scan(cnt);
+  F.pref[lane] = incl - cnt;
+  F.start[lane] = s;
+  if (lane == kWave - 1) F.pref[kWave] = incl;
+  wave_sync();
+  return __shfl(incl, kWave - 1, kWave);
+}
+
+// Same, from per-lane (start, count) already loaded (count 0 for masked lanes).
+DB_DEV int flatten_ranges(const Flat& F, int s, int cnt) {
+  const int lane = lane_id();
+  wave_sync();
   const int incl = wave_incl_scan(cnt);
   F.pref[lane] = incl - cnt;
   F.start[lane] = s;
@@ -162,11 +206,14 @@ DB_DEV void load_box(const TreeView& T, int c, Query<D>& q) {
 // the smaller with a CAS on the root, and path halving only ever stores an
 // ancestor, so racing finds and links stay consistent.
 // ---------------------------------------------------------------------------
+// Reads are plain (cacheable) loads: a stale parent is still an ancestor, so a
+// find may return a former root.  That only weakens pruning; links are decided by
+// the CAS in uf_link, which continues from the value it reads.
 DB_DEV int uf_find(int32_t* parent, int x) {
   while (true) {
-    const int p = ld_acq(&parent[x]);
+    const int p = parent[x];
     if (p == x) return x;
-    const int gp = ld_acq(&parent[p]);
+    const int gp = parent[p];
     if (gp != p) st_rel(&parent[x], gp);
     x = gp;
   }
@@ -332,6 +379,9 @@ template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
+  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
@@ -366,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
         else load_point<D>(W.X, n, ps + lane, v.p);
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk<D>(W.tree, C, q, v);
+      walk<D>(W.tree, C, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
       if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
       v.ctr.flush(W.desc);
     }
@@ -420,10 +470,17 @@ __global__ void k_setting_init(Work W) {
 template <int D, bool F32>
 struct BcpVisitor {
   static constexpr bool kNearestFirst = false;
+  // aligned 64-point chunks of the unit kept in registers, and whether the
+  // chunk boxes of the unit are kept in registers (one chunk per lane)
+  static constexpr bool kBoxRegs = false;
+  // the cell-by-cell path for dense groups (low dimensions only: in higher
+  // dimensions cells hold few points and the path would only cost registers)
+  static constexpr bool kDensePath = D <= 3;
   float tin, tout;
   const Work* W;
   Flat F;
   int ps, pe;      // sorted point range of the unit (its core points take part)
+  int c0, nchk;    // first aligned chunk of the unit and number of chunks
   int hmax;        // candidate cells are those with index < hmax
   int ucell;       // a core cell of the unit; links are made from it
   int rg;          // a root of the unit's component (refreshed per group; stale is safe)
@@ -431,7 +488,30 @@ struct BcpVisitor {
   int excl_level;  // node already covered by an earlier round (level, index), or -1
   int excl_idx;
   bool prune;      // node roots of the previous round are valid
+  int split, part; // this wave handles every split-th group of the walk, from part
+  int visit;
   Counters ctr;
+  double blo[D], bhi[D];  // (unused unless kBoxRegs)
+
+  DB_DEV void load_chunk(int c, double (&x)[D], float (&a)[D], int& cell, bool& v) const {
+    const int i = (c0 + c) * kWave + lane_id();
+    v = i >= ps && i < pe;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      x[d] = 0.0;
+      a[d] = 0.0f;
+    }
+    cell = -1;
+    if (v) {
+      const uint8_t core = W->coreS[i];
+      load_point<D>(W->X, W->n, i, x);
+      if constexpr (F32) {
+        load_local<D>(W->X32, W->n, i, a);
+        cell = W->cellOf[i];
+      }
+      v = core != 0;
+    }
+  }
 
   // A node is skipped when an earlier round already handled it, when it has no
   // core cell, or when all its core cells were in one component that the unit has
@@ -445,23 +525,150 @@ struct BcpVisitor {
     return uf_find(W->parent, r) != rg;
   }
 
+  // Dense groups: the live neighbour cells are taken one at a time; the q side is
+  // a contiguous run of the cell's points and the cell's box stands in for the box
+  // of each q chunk, so no chunk search or box reduction is needed.
+  DB_DEV void dense_cells(int cb, uint64_t alive, int hr, int s0, int s1) {
+    const int lane = lane_id();
+    const int n = W->n;
+    while (alive) {
+      const int c = __ffsll((long long)alive) - 1;
+      const int h = cb + c;
+      const int hs = bcast(s0, c), he = bcast(s1, c);
+      Query<D> hb;
+      load_box<D>(W->tree, h, hb);
+      // unit chunks farther than eps from h's box are skipped whole
+      uint64_t pmask_all = 0;
+      for (int pc0 = 0; pc0 < nchk; pc0 += kWave) {
+        const int pcl = pc0 + lane;
+        bool sv = false;
+        if constexpr (kBoxRegs) {
+          if (pc0 == 0) {
+            Query<D> cbx;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              cbx.lo[d] = blo[d];
+              cbx.hi[d] = bhi[d];
+            }
+            sv = pcl < nchk && box_sqdist<D>(hb.lo, hb.hi, cbx.lo, cbx.hi, 1, 0) <= W->E2;
+          } else if (pcl < nchk) {
+            sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+          }
+        } else if (pcl < nchk) {
+          sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+        }
+        if (pc0 == 0) pmask_all = ballot(sv);
+        else if (ballot(sv)) pmask_all = ~0ull;  // (more than 64 chunks: scan them all below)
+      }
+      bool linked_h = false;
+      for (int qb = hs; qb < he && !linked_h; qb += kWave) {
+        const int q = qb + lane;
+        bool valid = q < he;
+        double xq[D];
+        float aq[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          xq[d] = 0.0;
+          aq[d] = 0.0f;
+        }
+        if (valid) {
+          const uint8_t core = W->coreS[q];
+          load_point<D>(W->X, n, q, xq);
+          if constexpr (F32) load_local<D>(W->X32, n, q, aq);
+          valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
+        }
+        if (!ballot(valid)) continue;
+        uint64_t sm = nchk <= kWave ? pmask_all : ~0ull;
+        while (sm && !linked_h) {
+          const int cidx = __ffsll((long long)sm) - 1;
+          sm &= sm - 1;
+          if (cidx >= nchk) break;
+          const int chunk = c0 + cidx;
+          double xp[D];
+          float ap[D];
+          int pcell = -1;
+          bool pv = false;
+          load_chunk(cidx, xp, ap, pcell, pv);
+          pv = pv && box_sqdist<D>(xp, xp, hb.lo, hb.hi, 1, 0) <= W->E2;
+          uint64_t pm = ballot(pv);
+          int curcell = -1;
+          float off[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) off[d] = 0.0f;
+          while (pm) {
+            const int t = __ffsll((long long)pm) - 1;
+            pm &= pm - 1;
+            bool hit;
+            ctr.pairs += (unsigned long long)__popcll(ballot(valid));
+            if constexpr (F32) {
+              const int pc = bcast(pcell, t);
+              if (pc != curcell) {
+                curcell = pc;
+                double apc[D];
+                load_anchor<D>(W->tree, pc, apc);
+                anchor_offsets<D>(W->tree, apc, h, off);
+              }
+              float at[D];
+#pragma unroll
+              for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+              hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
+                                    ctr.rechecks);
+            } else {
+              double xt[D];
+#pragma unroll
+              for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
+              hit = valid && sqdist<D>(xt, xq) <= W->E2;
+            }
+            if (ballot(hit)) {
+              bool linked = false;
+              if (lane == 0) linked = uf_link(W->parent, ucell, h);
+              ctr.links += ballot(linked) ? 1ull : 0ull;
+              linked_h = true;
+              break;
+            }
+          }
+        }
+      }
+      if (linked_h) {
+        const int rc = bcast(hr, c);
+        alive &= ~ballot(hr == rc);  // that whole component has joined
+      }
+      alive &= ~(1ull << c);
+    }
+  }
+
   DB_DEV bool group(int cb, uint64_t m) {
+    if (visit++ % split != part) return false;
     const int lane = lane_id();
     const int n = W->n;
     const int h = cb + lane;
-    bool on = ((m >> lane) & 1ull) && h < hmax && W->coreCount[h] > 0;
+    const bool inm = ((m >> lane) & 1ull) && h < hmax;
+    // every per-cell load of the group at once
+    int cc = 0, s0 = 0, s1 = 0, par = -1;
+    if (inm) {
+      cc = W->coreCount[h];
+      s0 = W->cellStart[h];
+      s1 = W->cellStart[h + 1];
+      par = W->parent[h];
+    }
     rg = uf_find(W->parent, ucell);
+    bool on = inm && cc > 0;
     int hr = -1;
     if (on) {
-      hr = uf_find(W->parent, h);
+      hr = par == h ? h : uf_find(W->parent, par);
       on = hr != rg;
     }
     uint64_t alive = ballot(on);
     if (!alive) return false;
     ctr.bcp += (unsigned long long)__popcll(alive);
-    const int c0 = ps >> 6;
-    const int nchk = ((pe - 1) >> 6) - c0 + 1;
-    const int tot = flatten(F, W->cellStart, cb, alive);
+    if constexpr (kDensePath) {
+      const int tot_pts = wave_sum(on ? s1 - s0 : 0);
+      if (tot_pts >= kDenseGroup * __popcll(alive)) {
+        dense_cells(cb, alive, hr, on ? s0 : 0, on ? s1 : 0);
+        return false;
+      }
+    }
+    const int tot = flatten_ranges(F, on ? s0 : 0, on ? s1 - s0 : 0);
     for (int base = 0; base < tot && alive; base += kWave) {
       const int k = base + lane;
       bool valid = k < tot;
@@ -475,13 +682,12 @@ struct BcpVisitor {
       }
       if (valid) {
         locate(F, k, j, q);
-        valid = W->coreS[q] != 0 && ((alive >> j) & 1ull);
-      }
-      if (valid) {
+        const uint8_t core = W->coreS[q];
         load_point<D>(W->X, n, q, xq);
         if constexpr (F32) load_local<D>(W->X32, n, q, aq);
         // points of h farther than eps from the unit's box drop out
-        valid = box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
+        valid = core != 0 && ((alive >> j) & 1ull) &&
+                box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
       }
       if (!ballot(valid)) continue;
       double qlo[D], qhi[D];
@@ -496,34 +702,35 @@ struct BcpVisitor {
       for (int pc0 = 0; pc0 < nchk && !stop; pc0 += kWave) {
         const int pcl = pc0 + lane;
         bool sv = false;
-        if (pcl < nchk)
-          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+        if constexpr (kBoxRegs) {
+          if (pc0 == 0) {
+            Query<D> cbx;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              cbx.lo[d] = blo[d];
+              cbx.hi[d] = bhi[d];
+            }
+            sv = pcl < nchk && box_sqdist<D>(qlo, qhi, cbx.lo, cbx.hi, 1, 0) <= W->E2;
+          } else if (pcl < nchk) {
+            sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+          }
+        } else {
+          if (pcl < nchk)
+            sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+        }
         uint64_t sm = ballot(sv);
         while (sm && !stop) {
           const int b = __ffsll((long long)sm) - 1;
           sm &= sm - 1;
-          const int chunk = c0 + pc0 + b;
-          const int i = chunk * kWave + lane;
-          bool pv = i >= ps && i < pe && W->coreS[i] != 0;
+          const int cidx = pc0 + b;
+          const int chunk = c0 + cidx;
           double xp[D];
           float ap[D];
           int pcell = -1;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            xp[d] = 0.0;
-            ap[d] = 0.0f;
-          }
-          if (pv) {
-            // points of the unit farther than eps from this chunk's box drop out
-            load_point<D>(W->X, n, i, xp);
-            pv = box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
-            if constexpr (F32) {
-              if (pv) {
-                load_local<D>(W->X32, n, i, ap);
-                pcell = W->cellOf[i];
-              }
-            }
-          }
+          bool pv = false;
+          load_chunk(cidx, xp, ap, pcell, pv);
+          // points of the unit farther than eps from this chunk's box drop out
+          pv = pv && box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
           uint64_t pm = ballot(pv);
           int curcell = -1;
           float off[D];
@@ -590,13 +797,21 @@ template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
+  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
   const int C = W.desc->n_cells;
   int cnt[kTreeLevels + 2];
   level_counts(C, cnt);
   const int top = top_level(cnt);
   if (round > top) return;
   const int w = threadIdx.x / kWave;
-  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+  // W.bcp_split waves share one unit: each walks the unit's tree and handles every
+  // bcp_split-th neighbour group, so the dependent-load chain per wave is shorter.
+  const int split = W.bcp_split;
+  const long long nw = (long long)gridDim.x * kWavesPerBlock;
+  for (long long u = (long long)blockIdx.x * kWavesPerBlock + w; u < (long long)C * split; u += nw) {
+    const int g = (int)(u / split);
+    const int part = (int)(u % split);
     const int umax = round < 0 ? 0 : min(round, W.unit_max_level);
     int ulevel = -1;
     if (W.coreCount[g] > 0 && (umax == 0 || W.nroot[1][g >> 6] < 0)) ulevel = 0;
@@ -632,13 +847,18 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
         v.uq.hi[d] = W.tree.hi[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
       }
     }
+    v.c0 = v.ps >> 6;
+    v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
     v.rg = v.ucell;
+    v.split = split;
+    v.part = part;
+    v.visit = 0;
     v.excl_level = round >= 1 ? round : -1;
     v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
     v.prune = round >= 1;
     const int anc_level = round < 0 ? top + 1 : round + 1;
     const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
-    walk_subtree<D>(W.tree, cnt, anc_level, anc, v.uq, v);
+    walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
     v.ctr.flush(W.desc);
   }
 }
@@ -792,6 +1012,8 @@ template <int D, bool F32>
 __global__ __launch_bounds__(kBlock) void k_border(Work W) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
+  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
   __shared__ int s_pos[kWavesPerBlock][kWave];
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -847,7 +1069,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
         else load_point<D>(W.X, n, pos, v.p);
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk<D>(W.tree, C, q, v);
+      walk<D>(W.tree, C, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
       if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
       v.ctr.flush(W.desc);
     }

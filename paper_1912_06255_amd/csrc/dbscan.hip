@@ -29,6 +29,7 @@ struct dbscan_ctx {
   int fine_bits = -1;   // -1: automatic (0)
   int force_recheck = 0;
   int batch_graph = 1;
+  int bcp_split = 1;
   // profiling
   bool profile = false;
   bool events_ready = false;
@@ -203,19 +204,20 @@ void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds)
   const int64_t n = W.n;
   const unsigned gp = grid_for(n, kBlock, 2048);
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
+  const unsigned gb = grid_for(n * W.bcp_split, kWavesPerBlock, 8192);
   const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
   k_setting_init<<<1, 64, 0, s>>>(W);
   k_core_from_count<<<gw, kBlock, 0, s>>>(W);
   mark(7);
   if (!rounds) {
-    k_bcp<D, F32><<<gw, kBlock, 0, s>>>(W, -1);
+    k_bcp<D, F32><<<gb, kBlock, 0, s>>>(W, -1);
   } else {
     for (int round = 0; round < kTreeLevels; ++round) {
       if (round > 0) {
         for (int l = 1; l <= kTreeLevels; ++l)
           k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
       }
-      k_bcp<D, F32><<<gw, kBlock, 0, s>>>(W, round);
+      k_bcp<D, F32><<<gb, kBlock, 0, s>>>(W, round);
     }
   }
   mark(8);
@@ -268,6 +270,7 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
   W.unit_max_level = ctx->unit_level;
   W.force_recheck = ctx->force_recheck;
+  W.bcp_split = ctx->bcp_split;
   layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
 }
 
@@ -337,6 +340,7 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->unit_level);
   put(k, ctx->fine_bits);
   put(k, ctx->force_recheck);
+  put(k, ctx->bcp_split);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -548,6 +552,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return DBSCAN_EINVAL;
       ctx->batch_graph = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_BCP_SPLIT:
+      if (value < 1 || value > 64) return DBSCAN_EINVAL;
+      ctx->bcp_split = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -560,6 +568,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_FINE_BITS: *value = ctx->fine_bits; return DBSCAN_OK;
     case DBSCAN_OPT_FORCE_RECHECK: *value = ctx->force_recheck; return DBSCAN_OK;
     case DBSCAN_OPT_BATCH_GRAPH: *value = ctx->batch_graph; return DBSCAN_OK;
+    case DBSCAN_OPT_BCP_SPLIT: *value = ctx->bcp_split; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

@@ -31,6 +31,7 @@ struct Work {
   int unit_max_level; // largest tree level acting as one ClusterCore unit
   int force_recheck;  // filter mode: decide every pair in float64
   int count_cap;      // MarkCore counts neighbours up to this value (largest minPts of the eps)
+  int bcp_split;      // waves per ClusterCore unit
   double E2;
   double side;
   const double* pts;  // input, [n][D]
