@@ -386,7 +386,9 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
   const int cap = W.count_cap;
-  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+  const UnitRange R = xcd_units(C);
+  for (long long u = R.first; u < R.end; u += R.step) {
+    const int g = (int)u;
     const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
     if (m >= cap) {
       for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
@@ -808,8 +810,8 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
   // W.bcp_split waves share one unit: each walks the unit's tree and handles every
   // bcp_split-th neighbour group, so the dependent-load chain per wave is shorter.
   const int split = W.bcp_split;
-  const long long nw = (long long)gridDim.x * kWavesPerBlock;
-  for (long long u = (long long)blockIdx.x * kWavesPerBlock + w; u < (long long)C * split; u += nw) {
+  const UnitRange R = xcd_units((long long)C * split);
+  for (long long u = R.first; u < R.end; u += R.step) {
     const int g = (int)(u / split);
     const int part = (int)(u % split);
     const int umax = round < 0 ? 0 : min(round, W.unit_max_level);
@@ -1018,7 +1020,9 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
-  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+  const UnitRange R = xcd_units(C);
+  for (long long u = R.first; u < R.end; u += R.step) {
+    const int g = (int)u;
     const int s = W.cellStart[g], e = W.cellStart[g + 1];
     if (W.coreCount[g] == e - s) continue;
     Query<D> q;

@@ -11,6 +11,29 @@ namespace db {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;  // accelerator complex dies, each with its own L2
+
+// Units [0, total) of a wave-per-unit kernel in an XCD-aware order.  Workgroup b
+// runs on XCD b mod 8, so the units are cut into one contiguous range per XCD and
+// that XCD's waves stride through it: units that are close in Morton order (and
+// read each other's points) then share one L2 instead of being spread over all
+// eight.  Every unit is visited by exactly one wave for any grid size.
+struct UnitRange {
+  long long first, end, step;
+};
+
+DB_DEV UnitRange xcd_units(long long total) {
+  const int G = (int)gridDim.x;
+  const int X = G < kXcds ? G : kXcds;
+  const int x = (int)blockIdx.x % X;
+  const int r = (int)blockIdx.x / X;
+  const int per = (G - x + X - 1) / X;  // workgroups b < G with b mod X == x
+  const long long chunk = (total + X - 1) / X;
+  const long long b = total < (long long)x * chunk ? total : (long long)x * chunk;
+  const long long e = total < b + chunk ? total : b + chunk;
+  return UnitRange{b + (long long)r * kWavesPerBlock + (long long)(threadIdx.x / kWave), e,
+                   (long long)per * kWavesPerBlock};
+}
 constexpr int kSortItems = 8;
 constexpr int kTile = kBlock * kSortItems;  // keys per radix / scan tile
 

@@ -222,9 +222,17 @@ def test_filter_rechecks_exact_boundaries(gpu_lib):
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_exact_boundaries_4d_lattice(mode, gpu_lib):
+    """4D integer lattice with eps = 1: most neighbour pairs sit exactly at eps."""
+    rng = np.random.Generator(np.random.PCG64(305))
+    P = rng.integers(0, 12, size=(12000, 4)).astype(np.float64)
+    _assert_parity(P, 1.0, 6, mode, "4d lattice")
+
+
 @pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
                                   dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
-                                  dict(fine_bits=3), dict(fine_bits=0)])
+                                  dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=4)])
 @pytest.mark.parametrize("mode", MODES)
 def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
     n = 40_000
@@ -238,6 +246,6 @@ def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
         gx = gpu_dbscan(X, 200.0, 10, mode=mode, tag=f"opts {opts} 3d")
         gy = gpu_dbscan(Y, 2.0, 10, mode=mode, tag=f"opts {opts} 5d")
     finally:
-        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1)
+        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=1)
     assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
     assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
