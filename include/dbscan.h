@@ -180,8 +180,10 @@ const char *dbscan_phase_name(int32_t phase);
  *                          float64 recheck (for testing; default 0)
  *   DBSCAN_OPT_BATCH_GRAPH 1: dbscan_batch() captures and replays a HIP graph
  *                          (default); 0: it launches its kernels directly
- *   DBSCAN_OPT_BCP_SPLIT   waves per ClusterCore unit, each taking every k-th
- *                          neighbour group of the unit (1..64, default 1)
+ *   DBSCAN_OPT_BCP_SPLIT   most waves per ClusterCore unit: the unit's points
+ *                          are cut into up to this many segments of at least
+ *                          192 points, one wave each (1..64; -1: automatic,
+ *                          2 for one pass and 1 with rounds; the default)
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1

@@ -13,6 +13,11 @@ constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
 // by cell instead of flattening it.
 constexpr int kDenseGroup = 24;
+// Smallest segment of a ClusterCore unit handled by a wave of its own.
+#ifndef DB_BCP_SEGMENT
+#define DB_BCP_SEGMENT 192
+#endif
+constexpr int kBcpSegment = DB_BCP_SEGMENT;
 
 // ---------------------------------------------------------------------------
 // Tree walk.  Every node whose box can hold a point within eps of the query box
@@ -490,8 +495,6 @@ struct BcpVisitor {
   int excl_level;  // node already covered by an earlier round (level, index), or -1
   int excl_idx;
   bool prune;      // node roots of the previous round are valid
-  int split, part; // this wave handles every split-th group of the walk, from part
-  int visit;
   Counters ctr;
   double blo[D], bhi[D];  // (unused unless kBoxRegs)
 
@@ -534,6 +537,15 @@ struct BcpVisitor {
     const int lane = lane_id();
     const int n = W->n;
     while (alive) {
+      // Components merge while this wave works (other waves link concurrently):
+      // roots are refreshed before each test and cells already joined drop out.
+      {
+        const int ru = uf_find(W->parent, ucell);
+        const bool on = (alive >> lane) & 1ull;
+        if (on) hr = uf_find(W->parent, cb + lane);
+        alive &= ballot(on && hr != ru);
+        if (!alive) break;
+      }
       const int c = __ffsll((long long)alive) - 1;
       const int h = cb + c;
       const int hs = bcast(s0, c), he = bcast(s1, c);
@@ -640,7 +652,6 @@ struct BcpVisitor {
   }
 
   DB_DEV bool group(int cb, uint64_t m) {
-    if (visit++ % split != part) return false;
     const int lane = lane_id();
     const int n = W->n;
     const int h = cb + lane;
@@ -807,8 +818,11 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
   const int top = top_level(cnt);
   if (round > top) return;
   const int w = threadIdx.x / kWave;
-  // W.bcp_split waves share one unit: each walks the unit's tree and handles every
-  // bcp_split-th neighbour group, so the dependent-load chain per wave is shorter.
+  // Up to W.bcp_split waves share one unit: its points are cut into that many
+  // segments of at least kBcpSegment points, and each wave tests its segment
+  // against every neighbour, so a large cell no longer sets the kernel's length
+  // alone.  Links are made from the same cell, and a segment that finds its
+  // neighbour already joined (by another segment) skips it.
   const int split = W.bcp_split;
   const UnitRange R = xcd_units((long long)C * split);
   for (long long u = R.first; u < R.end; u += R.step) {
@@ -849,12 +863,17 @@ __global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
         v.uq.hi[d] = W.tree.hi[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
       }
     }
+    {
+      const int m = v.pe - v.ps;
+      const int nseg = max(1, min(split, m / kBcpSegment));
+      if (part >= nseg) continue;
+      const int len = (m + nseg - 1) / nseg;
+      v.ps += part * len;
+      v.pe = min(v.pe, v.ps + len);
+    }
     v.c0 = v.ps >> 6;
     v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
     v.rg = v.ucell;
-    v.split = split;
-    v.part = part;
-    v.visit = 0;
     v.excl_level = round >= 1 ? round : -1;
     v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
     v.prune = round >= 1;

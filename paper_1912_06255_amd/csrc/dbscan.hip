@@ -29,7 +29,7 @@ struct dbscan_ctx {
   int fine_bits = -1;   // -1: automatic (0)
   int force_recheck = 0;
   int batch_graph = 1;
-  int bcp_split = 1;
+  int bcp_split = -1;   // -1: automatic (2 for one pass, 1 with rounds)
   // profiling
   bool profile = false;
   bool events_ready = false;
@@ -259,6 +259,10 @@ Stages stages_for(int d, bool f32) {
   return Stages{nullptr, nullptr, nullptr};
 }
 
+bool rounds_for(const dbscan_ctx* ctx, int d) {
+  return ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
+}
+
 // Fields of Work shared by every stage of one grid.
 void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d, double eps) {
   std::memset(static_cast<void*>(&W), 0, sizeof(W));
@@ -270,12 +274,8 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
   W.unit_max_level = ctx->unit_level;
   W.force_recheck = ctx->force_recheck;
-  W.bcp_split = ctx->bcp_split;
+  W.bcp_split = ctx->bcp_split > 0 ? ctx->bcp_split : (rounds_for(ctx, d) ? 1 : 2);
   layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
-}
-
-bool rounds_for(const dbscan_ctx* ctx, int d) {
-  return ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
 }
 
 int check_args(int64_t n, int32_t d, double eps, int32_t min_pts) {
@@ -553,7 +553,7 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       ctx->batch_graph = (int)value;
       return DBSCAN_OK;
     case DBSCAN_OPT_BCP_SPLIT:
-      if (value < 1 || value > 64) return DBSCAN_EINVAL;
+      if (value < -1 || value == 0 || value > 64) return DBSCAN_EINVAL;
       ctx->bcp_split = (int)value;
       return DBSCAN_OK;
   }

@@ -232,7 +232,8 @@ def test_exact_boundaries_4d_lattice(mode, gpu_lib):
 
 @pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
                                   dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
-                                  dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=4)])
+                                  dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=1),
+                                  dict(bcp_split=4), dict(bcp_split=2, bcp_rounds=1)])
 @pytest.mark.parametrize("mode", MODES)
 def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
     n = 40_000
@@ -246,6 +247,6 @@ def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
         gx = gpu_dbscan(X, 200.0, 10, mode=mode, tag=f"opts {opts} 3d")
         gy = gpu_dbscan(Y, 2.0, 10, mode=mode, tag=f"opts {opts} 5d")
     finally:
-        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=1)
+        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1)
     assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
     assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
