@@ -35,7 +35,8 @@ struct Query {
 // Visitors provide:
 //   static constexpr bool kNearestFirst  enter child nodes by increasing box distance
 //   bool keep_node(int level, int idx)   false drops a node (level >= 1) unvisited
-//   bool group(int first_cell, uint64_t mask)
+//   bool group(int first_cell, uint64_t mask, double dist)   dist: this lane's cell box
+//                                        distance to the query (masked lanes only)
 //
 // The walk is iterative: one frame per tree level (the mask of children still to
 // enter, their first index and, for nearest-first walks, their box distances) is
@@ -76,7 +77,7 @@ DB_DEV void walk_subtree(const TreeView& T, int C, int level, int node, const Qu
   double dist;
   const uint64_t m0 = test_children<D>(T, C, level, node, q, vis, dist);
   if (level == 1) {
-    if (m0) vis.group(node * 64, m0);
+    if (m0) vis.group(node * 64, m0, dist);
     return;
   }
   int lvl = level;
@@ -107,7 +108,7 @@ DB_DEV void walk_subtree(const TreeView& T, int C, int level, int node, const Qu
     const uint64_t m2 = test_children<D>(T, C, lvl - 1, child, q, vis, d2);
     if (!m2) continue;
     if (lvl - 1 == 1) {
-      if (vis.group(child * 64, m2)) return;
+      if (vis.group(child * 64, m2, d2)) return;
     } else {
       --lvl;
       wave_sync();
@@ -314,6 +315,7 @@ struct MarkCoreVisitor {
   DB_DEV bool keep_node(int, int) const { return true; }
   const Work* W;
   Flat F;
+  int* order;        // [64] LDS: group-local cell of each flattened position
   int g, ps, pm;
   int cnt;           // lane t: count of point ps + t
   uint64_t pending;  // points of the batch still below minPts
@@ -323,12 +325,38 @@ struct MarkCoreVisitor {
   float tin, tout;
   Counters ctr;
 
-  DB_DEV bool group(int cb, uint64_t m) {
+  DB_DEV bool group(int cb, uint64_t m, double dist) {
     if (g >= cb && g < cb + 64) m &= ~(1ull << (g - cb));
     if (!m) return false;
     const int n = W->n;
-    const int tot = flatten(F, W->cellStart, cb, m);
     const int lane = lane_id();
+    // In low dimensions the group's cells are taken nearest first (by box distance
+    // to g), so that the counts reach count_cap after as few chunks as possible;
+    // in high dimensions the ranking costs more than it saves.
+    const bool on = (m >> lane) & 1ull;
+    int cs = 0, cn = 0;
+    if (on) {
+      cs = W->cellStart[cb + lane];
+      cn = W->cellStart[cb + lane + 1] - cs;
+    }
+    int rank = lane;  // identity order when everything fits one chunk
+    if (D <= 3 && wave_sum(cn) > kWave) {
+      // masked cells by (distance, lane), then the others by lane
+      const double dv = on ? dist : 0.0;
+      int r = 0;
+      for (uint64_t mm = m; mm; mm &= mm - 1) {
+        const int l = __ffsll((long long)mm) - 1;
+        const double dl = bcast(dv, l);
+        r += (dl < dv || (dl == dv && l < lane)) ? 1 : 0;
+      }
+      rank = on ? r : __popcll(m) + __popcll(~m & lanemask_lt());
+    }
+    wave_sync();
+    order[rank] = lane;
+    wave_sync();
+    const int src = order[lane];
+    wave_sync();
+    const int tot = flatten_ranges(F, __shfl(cs, src, kWave), __shfl(cn, src, kWave));
     for (int base = 0; base < tot; base += kWave) {
       const int k = base + lane;
       const bool valid = k < tot;
@@ -345,7 +373,7 @@ struct MarkCoreVisitor {
         locate(F, k, j, q);
         if constexpr (F32) {
           load_local<D>(W->X32, n, q, aq);
-          anchor_offsets<D>(W->tree, ag, cb + j, off);
+          anchor_offsets<D>(W->tree, ag, cb + order[j], off);
         } else {
           load_point<D>(W->X, n, q, xq);
         }
@@ -387,6 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
   __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
   __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
+  __shared__ int s_order[kWavesPerBlock][kWave];
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
@@ -406,6 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       MarkCoreVisitor<D, F32> v;
       v.W = &W;
       v.F = Flat{s_pref[w], s_start[w]};
+      v.order = s_order[w];
       v.g = g;
       v.ps = ps;
       v.pm = min(kWave, e - ps);
@@ -651,7 +681,7 @@ struct BcpVisitor {
     }
   }
 
-  DB_DEV bool group(int cb, uint64_t m) {
+  DB_DEV bool group(int cb, uint64_t m, double) {
     const int lane = lane_id();
     const int n = W->n;
     const int h = cb + lane;
@@ -967,7 +997,7 @@ struct BorderVisitor {
   float tin, tout;
   Counters ctr;
 
-  DB_DEV bool group(int cb, uint64_t m) {
+  DB_DEV bool group(int cb, uint64_t m, double) {
     const int lane = lane_id();
     const int n = W->n;
     if (g >= cb && g < cb + 64) m &= ~(1ull << (g - cb));
