@@ -470,12 +470,25 @@ __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
   for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
     const int s = W.cellStart[g], e = W.cellStart[g + 1];
     int cc = 0, mn = kIntMax;
-    for (int i = s + lane; i < e; i += kWave) {
-      const bool core = W.cnt[i] >= W.minPts;
-      W.coreS[i] = core ? 1 : 0;
-      if (core) {
-        ++cc;
-        mn = min(mn, W.perm[i]);
+    // 8 x 64 points per step, all loads issued before any is used: a large cell
+    // costs a few load latencies instead of one per 64 points
+    for (int i0 = s; i0 < e; i0 += 8 * kWave) {
+      int c[8], pm[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * kWave + lane;
+        c[u] = i < e ? W.cnt[i] : -1;
+        pm[u] = i < e ? W.perm[i] : kIntMax;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * kWave + lane;
+        const bool core = c[u] >= W.minPts;
+        if (i < e) W.coreS[i] = core ? 1 : 0;
+        if (core) {
+          ++cc;
+          mn = min(mn, pm[u]);
+        }
       }
     }
     cc = wave_sum(cc);
