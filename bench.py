@@ -82,6 +82,57 @@ def algorithmic_bytes_per_point(phase: str, d: int, f32: bool) -> float:
     return float(table.get(phase, 0.0))
 
 
+# Kernel behind each phase's roofline entry, as rocprofv3 names it.
+PHASE_KERNEL = {
+    "cluster_core": "void db::k_bcp<{d}, {f}>(db::Work, int)",
+    "markcore": "void db::k_markcore<{d}, {f}>(db::Work)",
+    "radix_sort": "db::k_sort_pass(db::Work, int, int)",
+    "border": "void db::k_border<{d}, {f}>(db::Work)",
+    "cells": "void db::k_cells<{d}>(db::Work, int)",
+    "keys": "void db::k_keys<{d}>(db::Work)",
+    "cell_boxes": "void db::k_cell_box<{d}>(db::Work, int)",
+    "scatter": "db::k_scatter(db::Work)",
+}
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the HIP sources (names and bytes), to tell whether stored
+    counter figures still describe the kernels that run."""
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1912_06255_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel factor), or None when
+    there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        line = next((ln for ln in f if ln.startswith("traffic-json: ")), None)
+    if line is None:
+        return None
+    rec = json.loads(line[len("traffic-json: "):])
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    k = rec["kernels"].get(kernel)
+    if k is None:
+        return None
+    sc = rec["scale"]
+    b = (k["fetch_kib"] * sc["FETCH_SIZE"] + k["write_kib"] * sc["WRITE_SIZE"]) * 1024.0
+    return b, (f"profiles/pmc_traffic_{workload}.md: (FETCH_SIZE x {sc['FETCH_SIZE']} + "
+               f"WRITE_SIZE x {sc['WRITE_SIZE']}) KiB per dispatch")
+
+
 def cpu_baseline(items, budget_s: float = 25.0):
     """Time the C oracle on the host cores on (a bounded prefix of) the workload."""
     from oracle.o1 import build_o1, dbscan_o1, o1_threads
@@ -211,15 +262,19 @@ def main() -> int:
     per_launch_ms = phase_ms[dom] / launches
     alg_bytes = algorithmic_bytes_per_point(dom, d0, True) * n0
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kname = PHASE_KERNEL.get(dom, dom).format(d=d0, f="true")
+    traffic, traffic_src = stored_traffic(args.workload, kname) or (None, None)
     roofline = {
         "bound": "hbm",
-        "kernel": dom,
+        "kernel": kname,
+        "phase": dom,
         "launches_per_step": launches,
         "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None,
+        "traffic": None if traffic is None else int(traffic),
+        "traffic_source": traffic_src,
         "avg_launch_ms": round(per_launch_ms, 5),
         "alg_bytes_per_launch": int(alg_bytes),
     }
