@@ -180,6 +180,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="spreader3d_n1e6", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the options on the first cloud and setting (both modes) "
+                         "before the timed legs; the tuning time is reported, not timed")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only run the workload a few times in each mode plus a reference "
                          "elementwise kernel of known size (256 MiB read, 256 MiB written), "
@@ -206,6 +209,13 @@ def main() -> int:
     outs = [[(torch.empty(X.shape[0], dtype=torch.uint8, device=dev),
               torch.empty(X.shape[0], dtype=torch.int32, device=dev)) for _ in st]
             for X, st in zip(clouds, settings)]
+
+    autotune = None
+    if args.tune:
+        t0 = time.perf_counter()
+        X0, (e0, m0) = clouds[0], settings[0][0]
+        autotune = {m: binding.tune(X0, e0, m0, mode=m) for m in ("fp64", "fp32_filter")}
+        autotune["seconds"] = time.perf_counter() - t0
 
     def unbatched(mode):
         def step():
@@ -299,6 +309,7 @@ def main() -> int:
         "filter_unbatched": {"value": rates["filter"][0], "ms_per_step": rates["filter"][1]},
         "speedup_batched_filter_vs_plain": value / rates["plain"][0],
         "graph_first_replay_ms": first_replay_ms,
+        "autotune": autotune,
         "roofline": roofline,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "profiled_ms_per_step": prof_wall * 1e3 / args.steps,

@@ -173,7 +173,7 @@ const char *dbscan_phase_name(int32_t phase);
  *                             the default)
  *   DBSCAN_OPT_UNIT_LEVEL  in rounds, tree nodes up to this level whose core
  *                          cells already form one component are tested as one
- *                          unit (0..5, default 1)
+ *                          unit (0..5; -1: automatic = 1, the default)
  *   DBSCAN_OPT_FINE_BITS   sub-cell Morton bits per dimension used to order the
  *                          points inside a cell (-1: automatic = 0, else 0..8)
  *   DBSCAN_OPT_FORCE_RECHECK  1: the float32 filter sends every pair to the
@@ -194,6 +194,40 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_BCP_SPLIT 6
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
+
+/*
+ * Autotuner over the tuning options (one pass or rounds, the unit level,
+ * waves per unit and sub-cell order bits).  dbscan_tune() runs the given
+ * instance with the default options and then changes one option at a time
+ * (two sweeps of coordinate descent; a change must be 2% faster), timing each
+ * candidate as the median of three runs with HIP events on `stream`.  The best
+ * set is stored in the context for the instance's class (d, mode and
+ * n in [2^k, 2^(k+1))), and later dbscan() / dbscan_batch() calls of that
+ * class use it for every option left automatic (-1); options set explicitly
+ * with dbscan_set_option() still win.  Results never depend on the options, so
+ * core_flags / cluster_id hold the instance's exact result afterwards.  The
+ * call synchronises with `stream`.  Returns DBSCAN_EINVAL for n == 0 or bad
+ * arguments (as dbscan()), or the first error of a run.
+ *
+ * dbscan_tune_save() writes the table as text ("dbscan-tune 1", then one line
+ * "d mode k rounds unit_level split fine_bits ms" per class);
+ * dbscan_tune_load() merges such a file into the table (a malformed file leaves
+ * the table unchanged and returns DBSCAN_EINVAL); dbscan_tune_clear() empties
+ * it.  None of the three touches the GPU.
+ */
+typedef struct dbscan_tuned {
+  int32_t bcp_rounds, unit_level, bcp_split, fine_bits; /* the chosen options */
+  float ms;         /* median time of one call with them */
+  float ms_default; /* the same with the default options */
+  int32_t trials;   /* option sets timed */
+  int32_t size_class; /* k: the class holds n in [2^k, 2^(k+1)) */
+} dbscan_tuned;
+int dbscan_tune(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d,
+                double eps, int32_t min_pts, int32_t mode, uint8_t *core_flags,
+                int32_t *cluster_id, void *stream, dbscan_tuned *out);
+int dbscan_tune_save(dbscan_ctx *ctx, const char *path);
+int dbscan_tune_load(dbscan_ctx *ctx, const char *path);
+int dbscan_tune_clear(dbscan_ctx *ctx);
 
 /* Static description of a return code. */
 const char *dbscan_strerror(int code);

@@ -70,6 +70,22 @@ class Instance(ctypes.Structure):
     ]
 
 
+class Tuned(ctypes.Structure):
+    _fields_ = [
+        ("bcp_rounds", ctypes.c_int32),
+        ("unit_level", ctypes.c_int32),
+        ("bcp_split", ctypes.c_int32),
+        ("fine_bits", ctypes.c_int32),
+        ("ms", ctypes.c_float),
+        ("ms_default", ctypes.c_float),
+        ("trials", ctypes.c_int32),
+        ("size_class", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _lock = threading.Lock()
 _ctx: dict[int, ctypes.c_void_p] = {}
@@ -98,11 +114,15 @@ def load():
     lib.dbscan_phase_times.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.dbscan_phase_name.argtypes = [i32]
     lib.dbscan_phase_name.restype = ctypes.c_char_p
+    lib.dbscan_tune.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp, ctypes.POINTER(Tuned)]
+    lib.dbscan_tune_save.argtypes = [vp, ctypes.c_char_p]
+    lib.dbscan_tune_load.argtypes = [vp, ctypes.c_char_p]
+    lib.dbscan_tune_clear.argtypes = [vp]
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
               "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option",
-              "dbscan_batch"):
+              "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -180,6 +200,43 @@ def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None,
     if check and n > 0:
         stats(dev, stream, raise_on_error=True)
     return core, label
+
+
+def tune(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None) -> dict:
+    """Autotune the options for ``points``' class (d, mode, size) and keep the
+    choice in the context; returns the chosen options and timings.  Synchronises."""
+    import torch
+
+    if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64
+            and points.dim() == 2):
+        raise TypeError("points must be a float64 CUDA tensor [n, d]")
+    points = points.contiguous()
+    n, d = points.shape
+    dev = points.device.index if points.device.index is not None else torch.cuda.current_device()
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.uint8, device=points.device),
+               torch.empty(n, dtype=torch.int32, device=points.device))
+    res = Tuned()
+    rc = load().dbscan_tune(
+        context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
+        ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
+        _stream_handle(dev, stream), ctypes.byref(res),
+    )
+    _check(rc, "dbscan_tune")
+    return res.as_dict()
+
+
+def tune_save(path: str, device: int = 0) -> None:
+    _check(load().dbscan_tune_save(context(device), os.fsencode(path)), "dbscan_tune_save")
+
+
+def tune_load(path: str, device: int = 0) -> None:
+    _check(load().dbscan_tune_load(context(device), os.fsencode(path)), "dbscan_tune_load")
+
+
+def tune_clear(device: int = 0) -> None:
+    _check(load().dbscan_tune_clear(context(device)), "dbscan_tune_clear")
 
 
 def stats(device: int = 0, stream=None, raise_on_error: bool = False) -> dict:

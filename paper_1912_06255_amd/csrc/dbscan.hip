@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -15,6 +16,25 @@
 #include "cluster.hpp"
 
 using namespace db;
+
+namespace {
+
+// Effective tuning options of one call (after automatic choices and the tuned table).
+struct Resolved {
+  int rounds;      // 0: one ClusterCore pass, 1: rounds over the tree levels
+  int unit_level;  // largest tree level acting as one unit in rounds
+  int split;       // most waves per ClusterCore unit
+  int fine;        // sub-cell Morton bits per dimension
+};
+
+// One tuned choice: instances of dimension d, mode and n in [2^lg, 2^(lg+1)).
+struct TunedEntry {
+  int d, mode, lg;
+  Resolved r;
+  float ms;
+};
+
+}  // namespace
 
 struct dbscan_ctx {
   int device = 0;
@@ -25,11 +45,14 @@ struct dbscan_ctx {
   int64_t last_n = 0;
   // tuning options
   int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
-  int unit_level = 1;
+  int unit_level = -1;  // -1: automatic (1)
   int fine_bits = -1;   // -1: automatic (0)
   int force_recheck = 0;
   int batch_graph = 1;
   int bcp_split = -1;   // -1: automatic (2 for one pass, 1 with rounds)
+  // autotuner: choices per (d, mode, size class), used where an option is automatic
+  std::vector<TunedEntry> tuned;
+  uint32_t tune_gen = 0;
   // profiling
   bool profile = false;
   bool events_ready = false;
@@ -259,22 +282,45 @@ Stages stages_for(int d, bool f32) {
   return Stages{nullptr, nullptr, nullptr};
 }
 
-bool rounds_for(const dbscan_ctx* ctx, int d) {
-  return ctx->bcp_rounds < 0 ? d > 3 : ctx->bcp_rounds != 0;
+int size_class(int64_t n) {
+  int lg = 0;
+  while (lg < 62 && (int64_t(1) << (lg + 1)) <= n) ++lg;
+  return lg;
+}
+
+const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
+  const int lg = size_class(n);
+  for (const TunedEntry& e : ctx->tuned)
+    if (e.d == d && e.mode == mode && e.lg == lg) return &e;
+  return nullptr;
+}
+
+// Explicit options win; automatic ones come from the tuned table, else from fixed
+// rules (one pass for d <= 3 with two waves per large unit, rounds above).
+Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
+  Resolved r{d > 3 ? 1 : 0, 1, 0, 0};
+  if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
+  if (ctx->bcp_rounds >= 0) r.rounds = ctx->bcp_rounds;
+  if (ctx->unit_level >= 0) r.unit_level = ctx->unit_level;
+  if (ctx->fine_bits >= 0) r.fine = ctx->fine_bits;
+  if (ctx->bcp_split > 0) r.split = ctx->bcp_split;
+  if (r.split <= 0) r.split = r.rounds ? 1 : 2;
+  return r;
 }
 
 // Fields of Work shared by every stage of one grid.
-void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d, double eps) {
+void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d, double eps,
+               const Resolved& R) {
   std::memset(static_cast<void*>(&W), 0, sizeof(W));
   W.n = (int)n;
   W.E2 = eps * eps;
   W.side = eps / std::sqrt((double)d);
   W.pts = points;
   W.desc = ctx->desc;
-  W.fine_max = ctx->fine_bits >= 0 ? ctx->fine_bits : 0;
-  W.unit_max_level = ctx->unit_level;
+  W.fine_max = R.fine;
+  W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
-  W.bcp_split = ctx->bcp_split > 0 ? ctx->bcp_split : (rounds_for(ctx, d) ? 1 : 2);
+  W.bcp_split = R.split;
   layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
 }
 
@@ -295,7 +341,8 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
     const dbscan_instance& I = inst[i];
     if (I.n == 0) continue;
     const Stages st = stages_for(I.d, f32);
-    const bool rounds = rounds_for(ctx, I.d);
+    const Resolved R = resolve(ctx, I.n, I.d, f32 ? DBSCAN_FP32_FILTER : DBSCAN_PLAIN_FP64);
+    const bool rounds = R.rounds != 0;
     std::vector<char> done((size_t)I.n_settings, 0);
     for (int32_t a = 0; a < I.n_settings; ++a) {
       if (done[a]) continue;
@@ -304,7 +351,7 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
       for (int32_t b = a; b < I.n_settings; ++b)
         if (I.eps[b] == eps) cap = std::max(cap, (int)I.min_pts[b]);
       Work W;
-      fill_work(ctx, W, I.points, I.n, I.d, eps);
+      fill_work(ctx, W, I.points, I.n, I.d, eps, R);
       W.count_cap = cap;
       st.grid(W, s, none, eps, first);
       first = false;
@@ -341,6 +388,7 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->fine_bits);
   put(k, ctx->force_recheck);
   put(k, ctx->bcp_split);
+  put(k, ctx->tune_gen);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -412,30 +460,22 @@ int dbscan_reserve(dbscan_ctx* ctx, int64_t n, int32_t d) {
   return grow(ctx, n, d);
 }
 
-int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
-           int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
-           void* stream) {
-  if (!ctx) return DBSCAN_EINVAL;
-  int rc = check_args(n, d, eps, min_pts);
-  if (rc != DBSCAN_OK) return rc;
-  if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
-  if (n == 0) {
-    ctx->last_n = 0;
-    return DBSCAN_OK;
-  }
-  if (!points || !core_flags || !cluster_id) return DBSCAN_EINVAL;
-  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
-  rc = grow(ctx, n, d);
-  if (rc != DBSCAN_OK) return rc;
+namespace {
 
+// One exact DBSCAN with the given options (arguments already checked, n > 0).
+int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+            int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
+            hipStream_t s, const Resolved& R) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  int rc = grow(ctx, n, d);
+  if (rc != DBSCAN_OK) return rc;
   Work W;
-  fill_work(ctx, W, points, n, d, eps);
+  fill_work(ctx, W, points, n, d, eps, R);
   W.count_cap = min_pts;
   W.minPts = min_pts;
   W.core_out = core_flags;
   W.label_out = cluster_id;
   ctx->last_n = n;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   if (ctx->profile && !ctx->events_ready) {
     for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i)
       if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return DBSCAN_EHIP;
@@ -446,8 +486,195 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   const Stages st = stages_for(d, mode == DBSCAN_FP32_FILTER);
   st.grid(W, s, mark, eps, true);
   st.count(W, s);
-  st.setting(W, s, mark, rounds_for(ctx, d));
+  st.setting(W, s, mark, R.rounds != 0);
   return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
+int check_call(const dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+               int32_t min_pts, int32_t mode, const uint8_t* core_flags,
+               const int32_t* cluster_id) {
+  if (!ctx) return DBSCAN_EINVAL;
+  const int rc = check_args(n, d, eps, min_pts);
+  if (rc != DBSCAN_OK) return rc;
+  if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
+  if (n > 0 && (!points || !core_flags || !cluster_id)) return DBSCAN_EINVAL;
+  return DBSCAN_OK;
+}
+
+}  // namespace
+
+int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+           int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
+           void* stream) {
+  const int rc = check_call(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id);
+  if (rc != DBSCAN_OK) return rc;
+  if (n == 0) {
+    ctx->last_n = 0;
+    return DBSCAN_OK;
+  }
+  return run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
+                 static_cast<hipStream_t>(stream), resolve(ctx, n, d, mode));
+}
+
+namespace {
+
+// Median of three timed runs of one option set (ms), or a negative error code.
+float time_options(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+                   int32_t min_pts, int32_t mode, uint8_t* core, int32_t* label, hipStream_t s,
+                   const Resolved& R, hipEvent_t e0, hipEvent_t e1, int* err) {
+  float t[3];
+  for (int k = 0; k < 3; ++k) {
+    if (hipEventRecord(e0, s) != hipSuccess) *err = DBSCAN_EHIP;
+    const int rc = run_one(ctx, points, n, d, eps, min_pts, mode, core, label, s, R);
+    if (rc != DBSCAN_OK) *err = rc;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      *err = DBSCAN_EHIP;
+    if (*err != DBSCAN_OK) return -1.0f;
+    if (hipEventElapsedTime(&t[k], e0, e1) != hipSuccess) *err = DBSCAN_EHIP;
+  }
+  std::sort(t, t + 3);
+  return t[1];
+}
+
+}  // namespace
+
+int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+                int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
+                void* stream, dbscan_tuned* out) {
+  int rc = check_call(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id);
+  if (rc != DBSCAN_OK) return rc;
+  if (n == 0) return DBSCAN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  const bool prof = ctx->profile;
+  ctx->profile = false;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DBSCAN_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DBSCAN_EHIP;
+  }
+  // start from the fixed rules (the tuned table of this class is ignored)
+  Resolved best{d > 3 ? 1 : 0, 1, d > 3 ? 1 : 2, 0};
+  int err = DBSCAN_OK;
+  // first run pays one-time costs (scratch growth, code loading); not timed
+  rc = run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s, best);
+  if (rc != DBSCAN_OK) err = rc;
+  int trials = 0;
+  float t_best = err == DBSCAN_OK ? time_options(ctx, points, n, d, eps, min_pts, mode, core_flags,
+                                                 cluster_id, s, best, e0, e1, &err)
+                                  : -1.0f;
+  const float t_default = t_best;
+  ++trials;
+  // coordinate descent over the options, two sweeps; a change must win by 2%
+  for (int sweep = 0; sweep < 2 && err == DBSCAN_OK; ++sweep) {
+    bool changed = false;
+    for (int opt = 0; opt < 4 && err == DBSCAN_OK; ++opt) {
+      static const int kVals[4][3] = {{0, 1, -1}, {1, 2, 4}, {0, 2, -1}, {0, 1, 2}};
+      for (int k = 0; k < 3 && err == DBSCAN_OK; ++k) {
+        const int v = kVals[opt][k];
+        if (v < 0) continue;
+        Resolved c = best;
+        int* field = opt == 0 ? &c.rounds : opt == 1 ? &c.split : opt == 2 ? &c.fine : &c.unit_level;
+        if (*field == v) continue;
+        if (opt == 3 && !c.rounds) continue;  // the unit level only acts in rounds
+        *field = v;
+        const float t = time_options(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
+                                     s, c, e0, e1, &err);
+        ++trials;
+        if (err == DBSCAN_OK && t < 0.98f * t_best) {
+          t_best = t;
+          best = c;
+          changed = true;
+        }
+      }
+    }
+    if (!changed) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->profile = prof;
+  if (err != DBSCAN_OK) return err;
+  const int lg = size_class(n);
+  bool found = false;
+  for (TunedEntry& e : ctx->tuned)
+    if (e.d == d && e.mode == mode && e.lg == lg) {
+      e.r = best;
+      e.ms = t_best;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back(TunedEntry{d, mode, lg, best, t_best});
+  ++ctx->tune_gen;
+  if (out) {
+    out->bcp_rounds = best.rounds;
+    out->unit_level = best.unit_level;
+    out->bcp_split = best.split;
+    out->fine_bits = best.fine;
+    out->ms = t_best;
+    out->ms_default = t_default;
+    out->trials = trials;
+    out->size_class = lg;
+  }
+  return DBSCAN_OK;
+}
+
+int dbscan_tune_save(dbscan_ctx* ctx, const char* path) {
+  if (!ctx || !path) return DBSCAN_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return DBSCAN_EINVAL;
+  std::fprintf(f, "dbscan-tune 1\n");
+  for (const TunedEntry& e : ctx->tuned)
+    std::fprintf(f, "%d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds, e.r.unit_level,
+                 e.r.split, e.r.fine, (double)e.ms);
+  return std::fclose(f) == 0 ? DBSCAN_OK : DBSCAN_EINVAL;
+}
+
+int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
+  if (!ctx || !path) return DBSCAN_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return DBSCAN_EINVAL;
+  int version = 0;
+  std::vector<TunedEntry> got;
+  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version == 1 ? DBSCAN_OK
+                                                                            : DBSCAN_EINVAL;
+  while (rc == DBSCAN_OK) {
+    TunedEntry e;
+    double ms = 0.0;
+    const int k = std::fscanf(f, "%d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg, &e.r.rounds,
+                              &e.r.unit_level, &e.r.split, &e.r.fine, &ms);
+    if (k == EOF) break;
+    const bool ok = k == 8 && e.d >= 1 && e.d <= DBSCAN_MAX_D &&
+                    (e.mode == DBSCAN_PLAIN_FP64 || e.mode == DBSCAN_FP32_FILTER) &&
+                    e.lg >= 0 && e.lg <= 62 && (e.r.rounds == 0 || e.r.rounds == 1) &&
+                    e.r.unit_level >= 0 && e.r.unit_level <= kTreeLevels && e.r.split >= 1 &&
+                    e.r.split <= 64 && e.r.fine >= 0 && e.r.fine <= 8;
+    if (!ok) {
+      rc = DBSCAN_EINVAL;
+      break;
+    }
+    e.ms = (float)ms;
+    got.push_back(e);
+  }
+  std::fclose(f);
+  if (rc != DBSCAN_OK) return rc;  // the table is left as it was
+  for (const TunedEntry& g : got) {
+    bool found = false;
+    for (TunedEntry& e : ctx->tuned)
+      if (e.d == g.d && e.mode == g.mode && e.lg == g.lg) {
+        e = g;
+        found = true;
+      }
+    if (!found) ctx->tuned.push_back(g);
+  }
+  ++ctx->tune_gen;
+  return DBSCAN_OK;
+}
+
+int dbscan_tune_clear(dbscan_ctx* ctx) {
+  if (!ctx) return DBSCAN_EINVAL;
+  ctx->tuned.clear();
+  ++ctx->tune_gen;
+  return DBSCAN_OK;
 }
 
 int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, int32_t mode,
@@ -537,7 +764,7 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       ctx->bcp_rounds = (int)value;
       return DBSCAN_OK;
     case DBSCAN_OPT_UNIT_LEVEL:
-      if (value < 0 || value > kTreeLevels) return DBSCAN_EINVAL;
+      if (value < -1 || value > kTreeLevels) return DBSCAN_EINVAL;
       ctx->unit_level = (int)value;
       return DBSCAN_OK;
     case DBSCAN_OPT_FINE_BITS:
