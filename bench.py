@@ -192,7 +192,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how it would shard); run with --gpus 1", file=sys.stderr)
+              "(the design notes describe how it would shard); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch

@@ -191,19 +191,19 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
   k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W);
   k_bbox_final<D><<<1, kBlock, 0, s>>>(W, (int)nb);
   mark(1);
-  k_keys<D><<<gp, kBlock, 0, s>>>(W);
+  // 512 workgroups: each merges its digit histograms into the global ones with
+  // one atomic per bin, so fewer, fuller workgroups contend less
+  k_keys<D><<<grid_for(n, kBlock, 512), kBlock, 0, s>>>(W);
   mark(2);
   for (int pass = 0; pass < 8; ++pass) k_sort_pass<<<tiles, kBlock, 0, s>>>(W, pass, (int)tiles);
   mark(3);
   k_cells<D><<<tiles, kBlock, 0, s>>>(W, 0);
   mark(4);
-  k_cell_box_init<D><<<gp, kBlock, 0, s>>>(W, 0);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 0);
   k_cell_safe<D><<<gp, kBlock, 0, s>>>(W);
   // cells that fail the float64 diameter guard become singletons
   k_cells<D><<<tiles, kBlock, 0, s>>>(W, 1);
   k_cells_copy<<<gp, kBlock, 0, s>>>(W);
-  k_cell_box_init<D><<<gp, kBlock, 0, s>>>(W, 1);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 1);
   mark(5);
   for (int l = 1; l <= kTreeLevels; ++l) {

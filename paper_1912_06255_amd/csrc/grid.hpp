@@ -123,7 +123,7 @@ __global__ void k_init(Work W, int first) {
 }
 
 // ---------------------------------------------------------------------------
-// a1: bounding box (partials per block, then one block finalises the grid).
+// Bounding box (partials per block, then one block finalises the grid).
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(Work W, int pass, int ntil
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3: cell runs.  mode 0: a new cell starts where the sorted key changes, and
+// Cell runs.  mode 0: a new cell starts where the sorted key changes, and
 // the points are gathered into cell order (SoA).  mode 1 (only when some cell
 // failed the diameter guard): additionally every point of an unsafe cell becomes
 // a cell of its own, written to the second set of cell arrays.
@@ -517,37 +517,24 @@ __global__ void k_cells_copy(Work W) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-cell float64 point boxes.  Cells fully inside a 64-point chunk are reduced
-// by a segmented wave scan and stored; cells crossing a chunk edge are combined
-// with atomics into boxes initialised to +inf / -inf.
+// Per-cell float64 point boxes (and the boxes of the aligned 64-point chunks).
+// Every cell's box is written exactly once, without atomics.
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ void k_cell_box_init(Work W, int only_if_split) {
-  const GridDesc* g = W.desc;
-  if (only_if_split && g->n_unsafe == 0) return;
-  const int C = g->n_cells, n = W.n;
-  double* lo = const_cast<double*>(W.tree.lo[0]);
-  double* hi = const_cast<double*>(W.tree.hi[0]);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      lo[(size_t)k * n + c] = __builtin_inf();
-      hi[(size_t)k * n + c] = -__builtin_inf();
-    }
-  }
-}
-
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) {
   const GridDesc* g = W.desc;
   if (only_if_split && g->n_unsafe == 0) return;
   const int n = W.n;
+  const int C = g->n_cells;
   double* lo = const_cast<double*>(W.tree.lo[0]);
   double* hi = const_cast<double*>(W.tree.hi[0]);
   const int lane = lane_id();
+  const int wid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int nw = gridDim.x * kWavesPerBlock;
   const int nchunks = (n + kWave - 1) / kWave;
-  for (int ch = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; ch < nchunks;
-       ch += gridDim.x * kWavesPerBlock) {
+  // (1) Per aligned 64-point chunk: boxes of the cells lying wholly inside it
+  // (segmented wave reduction) and the box of the chunk itself.
+  for (int ch = wid; ch < nchunks; ch += nw) {
     const int base = ch * kWave;
     const int i = base + lane;
     const bool valid = i < n;
@@ -558,8 +545,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
     if (last) owned = W.cellStart[c] >= base && W.cellStart[c + 1] <= base + kWave;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      double a = valid ? W.X[(size_t)k * n + i] : 0.0;
-      double b = a;
+      const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
+      double a = x, b = x;
 #pragma unroll
       for (int o = 1; o < kWave; o <<= 1) {
         const double ua = __shfl_up(a, o, kWave);
@@ -570,24 +557,57 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
           b = fmax(b, ub);
         }
       }
-      if (last) {
-        if (owned) {
-          lo[(size_t)k * n + c] = a;
-          hi[(size_t)k * n + c] = b;
-        } else {
-          atomic_min_double(&lo[(size_t)k * n + c], a);
-          atomic_max_double(&hi[(size_t)k * n + c], b);
-        }
+      if (owned) {
+        lo[(size_t)k * n + c] = a;
+        hi[(size_t)k * n + c] = b;
       }
       if (!only_if_split) {
-        // box of the whole aligned chunk (independent of cell boundaries)
-        const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
         const double ca = wave_min(valid ? x : __builtin_inf());
         const double cb = wave_max(valid ? x : -__builtin_inf());
         if (lane == 0) {
           W.chunkLo[(size_t)k * W.chunkCap + ch] = ca;
           W.chunkHi[(size_t)k * W.chunkCap + ch] = cb;
         }
+      }
+    }
+  }
+  // (2) Cells spanning more than one chunk: one wave per cell, U x 64 points per
+  // step with every load issued before the reduction, so a large cell costs a few
+  // load latencies (and no atomics).
+  constexpr int U = D <= 3 ? 8 : 4;
+  for (int c = wid; c < C; c += nw) {
+    const int s = W.cellStart[c], e = W.cellStart[c + 1];
+    if ((s >> 6) == ((e - 1) >> 6)) continue;  // inside one chunk: done in (1)
+    double a[D], b[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      a[k] = __builtin_inf();
+      b[k] = -__builtin_inf();
+    }
+    for (int i0 = s; i0 < e; i0 += U * kWave) {
+      double x[U][D];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kWave + lane;
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[u][k] = i < e ? W.X[(size_t)k * n + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool v = i0 + u * kWave + lane < e;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          a[k] = v ? fmin(a[k], x[u][k]) : a[k];
+          b[k] = v ? fmax(b[k], x[u][k]) : b[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double ra = wave_min(a[k]), rb = wave_max(b[k]);
+      if (lane == 0) {
+        lo[(size_t)k * n + c] = ra;
+        hi[(size_t)k * n + c] = rb;
       }
     }
   }
