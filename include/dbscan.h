@@ -57,7 +57,8 @@ extern "C" {
 /* Distance arithmetic of the pairwise decisions.  Both modes return identical
  * outputs: DBSCAN_FP32_FILTER decides most pairs from float32 cell-local
  * coordinates with a proven error band and re-decides in float64 the pairs whose
- * float32 result falls inside the band. */
+ * float32 result falls inside the band (by default for d <= 3 only; see
+ * DBSCAN_OPT_FILTER_MAX_D). */
 #define DBSCAN_PLAIN_FP64 0
 #define DBSCAN_FP32_FILTER 1
 
@@ -184,6 +185,11 @@ const char *dbscan_phase_name(int32_t phase);
  *                          are cut into up to this many segments of at least
  *                          192 points, one wave each (1..64; -1: automatic,
  *                          2 for one pass and 1 with rounds; the default)
+ *   DBSCAN_OPT_FILTER_MAX_D  DBSCAN_FP32_FILTER calls take their pair decisions
+ *                          through the float32 filter only for d up to this
+ *                          value; above it they decide in float64 directly
+ *                          (0..8; -1: automatic = 3, the default).  Results
+ *                          are the same either way.
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -192,6 +198,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_FORCE_RECHECK 4
 #define DBSCAN_OPT_BATCH_GRAPH 5
 #define DBSCAN_OPT_BCP_SPLIT 6
+#define DBSCAN_OPT_FILTER_MAX_D 7
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

@@ -50,6 +50,7 @@ struct dbscan_ctx {
   int force_recheck = 0;
   int batch_graph = 1;
   int bcp_split = -1;   // -1: automatic (2 for one pass, 1 with rounds)
+  int filter_max_d = -1;  // -1: automatic (3)
   // autotuner: choices per (d, mode, size class), used where an option is automatic
   std::vector<TunedEntry> tuned;
   uint32_t tune_gen = 0;
@@ -282,6 +283,15 @@ Stages stages_for(int d, bool f32) {
   return Stages{nullptr, nullptr, nullptr};
 }
 
+// Whether a call in `mode` takes its pair decisions through the float32 filter:
+// only up to filter_max_d dimensions (on this GPU unpacked float32 runs at the
+// float64 rate, and in higher dimensions the per-cell anchors cost more loads
+// than the float32 coordinates save, so there float64 decides directly).
+bool use_filter(const dbscan_ctx* ctx, int mode, int d) {
+  const int maxd = ctx->filter_max_d >= 0 ? ctx->filter_max_d : 3;
+  return mode == DBSCAN_FP32_FILTER && d <= maxd;
+}
+
 int size_class(int64_t n) {
   int lg = 0;
   while (lg < 62 && (int64_t(1) << (lg + 1)) <= n) ++lg;
@@ -340,8 +350,9 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
     if (I.n == 0) continue;
-    const Stages st = stages_for(I.d, f32);
-    const Resolved R = resolve(ctx, I.n, I.d, f32 ? DBSCAN_FP32_FILTER : DBSCAN_PLAIN_FP64);
+    const int mode = f32 ? DBSCAN_FP32_FILTER : DBSCAN_PLAIN_FP64;
+    const Stages st = stages_for(I.d, use_filter(ctx, mode, I.d));
+    const Resolved R = resolve(ctx, I.n, I.d, mode);
     const bool rounds = R.rounds != 0;
     std::vector<char> done((size_t)I.n_settings, 0);
     for (int32_t a = 0; a < I.n_settings; ++a) {
@@ -389,6 +400,7 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->force_recheck);
   put(k, ctx->bcp_split);
   put(k, ctx->tune_gen);
+  put(k, ctx->filter_max_d);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -483,7 +495,7 @@ int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double 
   }
   const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
   ctx->events_recorded = ctx->profile;
-  const Stages st = stages_for(d, mode == DBSCAN_FP32_FILTER);
+  const Stages st = stages_for(d, use_filter(ctx, mode, d));
   st.grid(W, s, mark, eps, true);
   st.count(W, s);
   st.setting(W, s, mark, R.rounds != 0);
@@ -783,6 +795,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value < -1 || value == 0 || value > 64) return DBSCAN_EINVAL;
       ctx->bcp_split = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_FILTER_MAX_D:
+      if (value < -1 || value > DBSCAN_MAX_D) return DBSCAN_EINVAL;
+      ctx->filter_max_d = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -796,6 +812,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_FORCE_RECHECK: *value = ctx->force_recheck; return DBSCAN_OK;
     case DBSCAN_OPT_BATCH_GRAPH: *value = ctx->batch_graph; return DBSCAN_OK;
     case DBSCAN_OPT_BCP_SPLIT: *value = ctx->bcp_split; return DBSCAN_OK;
+    case DBSCAN_OPT_FILTER_MAX_D: *value = ctx->filter_max_d; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

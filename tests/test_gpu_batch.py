@@ -44,13 +44,19 @@ def _clouds():
     return [A, B, C, E], settings
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
-def test_batch_matches_oracle(mode, gpu_lib):
+@pytest.mark.parametrize("mode,filter_max_d", [("fp64", -1), ("fp32_filter", -1), ("fp32_filter", 8)])
+def test_batch_matches_oracle(mode, filter_max_d, gpu_lib):
+    from paper_1912_06255_amd import binding
+
     clouds, settings = _clouds()
-    b = _batch(clouds, settings, mode)
-    log(f"batch mode={mode} clouds={len(clouds)}")
-    b.run()
-    _check_batch(b, clouds, settings, f"batch {mode}")
+    binding.set_option("filter_max_d", filter_max_d)
+    try:
+        b = _batch(clouds, settings, mode)
+        log(f"batch mode={mode} filter_max_d={filter_max_d} clouds={len(clouds)}")
+        b.run()
+        _check_batch(b, clouds, settings, f"batch {mode}")
+    finally:
+        binding.set_option("filter_max_d", -1)
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])

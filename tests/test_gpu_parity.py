@@ -64,12 +64,24 @@ def test_high_dim(d, eps, mode, gpu_lib):
     rng = np.random.Generator(np.random.PCG64(203 + d))
     X = gaussian_mixture(8000, d, 12, 1.0, 16.0, 0.05, rng)
     _assert_parity(X, eps, 10, mode, f"mixture d={d} eps={eps}")
+    if mode == "fp32_filter":
+        # the float32 filter path itself, which is off by default above 3 dimensions
+        try:
+            _set_opts(filter_max_d=8)
+            _assert_parity(X, eps, 10, mode, f"mixture d={d} eps={eps} filter forced")
+        finally:
+            _set_opts(filter_max_d=-1)
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_multi_cloud_small(mode, gpu_lib):
-    for i, inst in enumerate(multi_cloud_batch(n_clouds=16, size_scale=0.01)):
-        _assert_parity(inst.X, inst.eps[0], inst.min_pts[0], mode, f"cloud {i} d={inst.d}")
+@pytest.mark.parametrize("filter_max_d", [-1, 8])
+def test_multi_cloud_small(mode, filter_max_d, gpu_lib):
+    try:
+        _set_opts(filter_max_d=filter_max_d)
+        for i, inst in enumerate(multi_cloud_batch(n_clouds=16, size_scale=0.01)):
+            _assert_parity(inst.X, inst.eps[0], inst.min_pts[0], mode, f"cloud {i} d={inst.d}")
+    finally:
+        _set_opts(filter_max_d=-1)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -203,10 +215,10 @@ def test_filter_forced_recheck_equals_plain(d, gpu_lib):
     eps = 1.2 if d <= 3 else 2.0
     plain, st0 = gpu_dbscan(X, eps, 8, mode="fp64", tag=f"plain d={d}", want_stats=True)
     try:
-        _set_opts(force_recheck=1)
+        _set_opts(force_recheck=1, filter_max_d=8)
         forced, st1 = gpu_dbscan(X, eps, 8, mode="fp32_filter", tag=f"forced d={d}", want_stats=True)
     finally:
-        _set_opts(force_recheck=0)
+        _set_opts(force_recheck=0, filter_max_d=-1)
     assert st1["fp64_rechecks"] > 0
     assert np.array_equal(plain[0], forced[0]) and np.array_equal(plain[1], forced[1])
 
