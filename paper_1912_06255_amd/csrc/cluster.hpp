@@ -520,9 +520,6 @@ __global__ void k_setting_init(Work W) {
 template <int D, bool F32>
 struct BcpVisitor {
   static constexpr bool kNearestFirst = false;
-  // aligned 64-point chunks of the unit kept in registers, and whether the
-  // chunk boxes of the unit are kept in registers (one chunk per lane)
-  static constexpr bool kBoxRegs = false;
   // the cell-by-cell path for dense groups (low dimensions only: in higher
   // dimensions cells hold few points and the path would only cost registers)
   static constexpr bool kDensePath = D <= 3;
@@ -539,7 +536,6 @@ struct BcpVisitor {
   int excl_idx;
   bool prune;      // node roots of the previous round are valid
   Counters ctr;
-  double blo[D], bhi[D];  // (unused unless kBoxRegs)
 
   DB_DEV void load_chunk(int c, double (&x)[D], float (&a)[D], int& cell, bool& v) const {
     const int i = (c0 + c) * kWave + lane_id();
@@ -579,16 +575,19 @@ struct BcpVisitor {
   DB_DEV void dense_cells(int cb, uint64_t alive, int hr, int s0, int s1) {
     const int lane = lane_id();
     const int n = W->n;
+    bool fresh = true;  // the roots were just taken by group()
     while (alive) {
       // Components merge while this wave works (other waves link concurrently):
-      // roots are refreshed before each test and cells already joined drop out.
-      {
+      // roots are refreshed before each further test and cells already joined
+      // drop out.
+      if (!fresh) {
         const int ru = uf_find(W->parent, ucell);
         const bool on = (alive >> lane) & 1ull;
         if (on) hr = uf_find(W->parent, cb + lane);
         alive &= ballot(on && hr != ru);
         if (!alive) break;
       }
+      fresh = false;
       const int c = __ffsll((long long)alive) - 1;
       const int h = cb + c;
       const int hs = bcast(s0, c), he = bcast(s1, c);
@@ -599,21 +598,8 @@ struct BcpVisitor {
       for (int pc0 = 0; pc0 < nchk; pc0 += kWave) {
         const int pcl = pc0 + lane;
         bool sv = false;
-        if constexpr (kBoxRegs) {
-          if (pc0 == 0) {
-            Query<D> cbx;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              cbx.lo[d] = blo[d];
-              cbx.hi[d] = bhi[d];
-            }
-            sv = pcl < nchk && box_sqdist<D>(hb.lo, hb.hi, cbx.lo, cbx.hi, 1, 0) <= W->E2;
-          } else if (pcl < nchk) {
-            sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-          }
-        } else if (pcl < nchk) {
+        if (pcl < nchk)
           sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-        }
         if (pc0 == 0) pmask_all = ballot(sv);
         else if (ballot(sv)) pmask_all = ~0ull;  // (more than 64 chunks: scan them all below)
       }
@@ -758,22 +744,8 @@ struct BcpVisitor {
       for (int pc0 = 0; pc0 < nchk && !stop; pc0 += kWave) {
         const int pcl = pc0 + lane;
         bool sv = false;
-        if constexpr (kBoxRegs) {
-          if (pc0 == 0) {
-            Query<D> cbx;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              cbx.lo[d] = blo[d];
-              cbx.hi[d] = bhi[d];
-            }
-            sv = pcl < nchk && box_sqdist<D>(qlo, qhi, cbx.lo, cbx.hi, 1, 0) <= W->E2;
-          } else if (pcl < nchk) {
-            sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-          }
-        } else {
-          if (pcl < nchk)
-            sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-        }
+        if (pcl < nchk)
+          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
         uint64_t sm = ballot(sv);
         while (sm && !stop) {
           const int b = __ffsll((long long)sm) - 1;
@@ -850,7 +822,10 @@ struct BcpVisitor {
 // cells repeating the same links.
 // round = -1: a single pass in which every core cell walks the whole tree.
 template <int D, bool F32>
-__global__ __launch_bounds__(kBlock) void k_bcp(Work W, int round) {
+#ifndef DB_BCP_MINW
+#define DB_BCP_MINW 4
+#endif
+__global__ __launch_bounds__(kBlock, DB_BCP_MINW) void k_bcp(Work W, int round) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
   __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];

@@ -211,10 +211,7 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
     const int64_t nodes = W.tree.cap[l];
     k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
   }
-  if (F32) {
-    k_thresholds<D><<<1, 64, 0, s>>>(W, eps);
-    k_local32<D><<<gp, kBlock, 0, s>>>(W);
-  }
+  if (F32) k_local32<D><<<gp, kBlock, 0, s>>>(W, eps);
   mark(6);
 }
 

@@ -34,7 +34,10 @@ DB_DEV UnitRange xcd_units(long long total) {
   return UnitRange{b + (long long)r * kWavesPerBlock + (long long)(threadIdx.x / kWave), e,
                    (long long)per * kWavesPerBlock};
 }
-constexpr int kSortItems = 8;
+#ifndef DB_SORT_ITEMS
+#define DB_SORT_ITEMS 16
+#endif
+constexpr int kSortItems = DB_SORT_ITEMS;
 constexpr int kTile = kBlock * kSortItems;  // keys per radix / scan tile
 
 // Look-back epoch slots within one call: 0..7 radix passes, 8..9 cell scans.
@@ -658,8 +661,7 @@ __global__ void k_cell_safe(Work W) {
 // Both are widened by 2^-40 for the rounding of this computation and rounded
 // outwards to float32.  Outside a safe exponent range every pair is rechecked.
 template <int D>
-__global__ void k_thresholds(Work W, double eps) {
-  if (threadIdx.x != 0) return;
+DB_DEV void thresholds(const Work& W, double eps) {
   GridDesc* g = W.desc;
   const double u = 0x1p-24, v = 0x1p-53;
   const double M = __longlong_as_double((long long)g->max_extent_bits) * (1.0 + 0x1p-40);
@@ -683,9 +685,11 @@ __global__ void k_thresholds(Work W, double eps) {
   g->tout = __double2float_ru(tout);
 }
 
-// Float32 coordinates relative to the anchor of each point's cell (its box corner).
+// Float32 coordinates relative to the anchor of each point's cell (its box corner);
+// the first thread also sets the thresholds.
 template <int D>
-__global__ void k_local32(Work W) {
+__global__ void k_local32(Work W, double eps) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) thresholds<D>(W, eps);
   const int n = W.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int c = W.cellOf[i];

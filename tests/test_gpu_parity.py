@@ -139,8 +139,8 @@ def test_edge_cases(mode, gpu_lib):
     _assert_parity(Y, 0.3, 300, mode, "minPts 300")
     _assert_parity(rng.uniform(0, 100, size=(7000, 1)), 0.05, 3, mode, "d=1")
     _assert_parity(rng.normal(0, 1, size=(5000, 8)), 2.0, 6, mode, "d=8")
-    # ragged sizes around tile edges (radix tiles of 2048 points, waves of 64)
-    for n in (63, 64, 65, 2047, 2048, 2049, 4097):
+    # ragged sizes around tile edges (radix tiles of 4096 points, waves of 64)
+    for n in (63, 64, 65, 2047, 2049, 4095, 4096, 4097, 8193):
         Z = rng.uniform(0, 30, size=(n, 2))
         _assert_parity(Z, 1.0, 3, mode, f"ragged n={n}")
 
