@@ -822,10 +822,9 @@ struct BcpVisitor {
 // cells repeating the same links.
 // round = -1: a single pass in which every core cell walks the whole tree.
 template <int D, bool F32>
-#ifndef DB_BCP_MINW
-#define DB_BCP_MINW 4
-#endif
-__global__ __launch_bounds__(kBlock, DB_BCP_MINW) void k_bcp(Work W, int round) {
+// Four waves per SIMD where that fits without spilling (float64, d <= 4); the other
+// instantiations need more registers and would spill to scratch.
+__global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, int round) {
   __shared__ int s_pref[kWavesPerBlock][kWave + 1];
   __shared__ int s_start[kWavesPerBlock][kWave];
   __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
