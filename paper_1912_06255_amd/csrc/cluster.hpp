@@ -593,16 +593,17 @@ struct BcpVisitor {
       const int hs = bcast(s0, c), he = bcast(s1, c);
       Query<D> hb;
       load_box<D>(W->tree, h, hb);
-      // unit chunks farther than eps from h's box are skipped whole
-      uint64_t pmask_all = 0;
-      for (int pc0 = 0; pc0 < nchk; pc0 += kWave) {
+      // Unit chunks farther than eps from h's box are skipped whole.  The chunks
+      // are taken in windows of 64 (one per lane); the mask of a unit with a
+      // single window is computed once per h, larger units recompute it per window.
+      auto window_mask = [&](int pc0) {
         const int pcl = pc0 + lane;
         bool sv = false;
         if (pcl < nchk)
           sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-        if (pc0 == 0) pmask_all = ballot(sv);
-        else if (ballot(sv)) pmask_all = ~0ull;  // (more than 64 chunks: scan them all below)
-      }
+        return ballot(sv);
+      };
+      const uint64_t mask0 = nchk <= kWave ? window_mask(0) : 0ull;
       bool linked_h = false;
       for (int qb = hs; qb < he && !linked_h; qb += kWave) {
         const int q = qb + lane;
@@ -621,53 +622,54 @@ struct BcpVisitor {
           valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
         }
         if (!ballot(valid)) continue;
-        uint64_t sm = nchk <= kWave ? pmask_all : ~0ull;
-        while (sm && !linked_h) {
-          const int cidx = __ffsll((long long)sm) - 1;
-          sm &= sm - 1;
-          if (cidx >= nchk) break;
-          const int chunk = c0 + cidx;
-          double xp[D];
-          float ap[D];
-          int pcell = -1;
-          bool pv = false;
-          load_chunk(cidx, xp, ap, pcell, pv);
-          pv = pv && box_sqdist<D>(xp, xp, hb.lo, hb.hi, 1, 0) <= W->E2;
-          uint64_t pm = ballot(pv);
-          int curcell = -1;
-          float off[D];
+        for (int pc0 = 0; pc0 < nchk && !linked_h; pc0 += kWave) {
+          uint64_t sm = nchk <= kWave ? mask0 : window_mask(pc0);
+          while (sm && !linked_h) {
+            const int cidx = pc0 + __ffsll((long long)sm) - 1;
+            sm &= sm - 1;
+            const int chunk = c0 + cidx;
+            double xp[D];
+            float ap[D];
+            int pcell = -1;
+            bool pv = false;
+            load_chunk(cidx, xp, ap, pcell, pv);
+            pv = pv && box_sqdist<D>(xp, xp, hb.lo, hb.hi, 1, 0) <= W->E2;
+            uint64_t pm = ballot(pv);
+            int curcell = -1;
+            float off[D];
 #pragma unroll
-          for (int d = 0; d < D; ++d) off[d] = 0.0f;
-          while (pm) {
-            const int t = __ffsll((long long)pm) - 1;
-            pm &= pm - 1;
-            bool hit;
-            ctr.pairs += (unsigned long long)__popcll(ballot(valid));
-            if constexpr (F32) {
-              const int pc = bcast(pcell, t);
-              if (pc != curcell) {
-                curcell = pc;
-                double apc[D];
-                load_anchor<D>(W->tree, pc, apc);
-                anchor_offsets<D>(W->tree, apc, h, off);
+            for (int d = 0; d < D; ++d) off[d] = 0.0f;
+            while (pm) {
+              const int t = __ffsll((long long)pm) - 1;
+              pm &= pm - 1;
+              bool hit;
+              ctr.pairs += (unsigned long long)__popcll(ballot(valid));
+              if constexpr (F32) {
+                const int pc = bcast(pcell, t);
+                if (pc != curcell) {
+                  curcell = pc;
+                  double apc[D];
+                  load_anchor<D>(W->tree, pc, apc);
+                  anchor_offsets<D>(W->tree, apc, h, off);
+                }
+                float at[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+                hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
+                                      ctr.rechecks);
+              } else {
+                double xt[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
+                hit = valid && sqdist<D>(xt, xq) <= W->E2;
               }
-              float at[D];
-#pragma unroll
-              for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-              hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
-                                    ctr.rechecks);
-            } else {
-              double xt[D];
-#pragma unroll
-              for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
-              hit = valid && sqdist<D>(xt, xq) <= W->E2;
-            }
-            if (ballot(hit)) {
-              bool linked = false;
-              if (lane == 0) linked = uf_link(W->parent, ucell, h);
-              ctr.links += ballot(linked) ? 1ull : 0ull;
-              linked_h = true;
-              break;
+              if (ballot(hit)) {
+                bool linked = false;
+                if (lane == 0) linked = uf_link(W->parent, ucell, h);
+                ctr.links += ballot(linked) ? 1ull : 0ull;
+                linked_h = true;
+                break;
+              }
             }
           }
         }

@@ -117,6 +117,30 @@ def test_unsafe_cells_split(d, eps, mode, gpu_lib):
 
 
 @pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("big_first", [False, True])
+def test_large_cell_bridge(mode, d, big_first, gpu_lib):
+    """Two core cells joined by a single pair whose point in the large cell (10,000
+    points: more than 64 chunks of 64 even after the unit is split in two) comes
+    last in that cell, so that only a full scan of the large side finds it."""
+    rng = np.random.Generator(np.random.PCG64(501 + d))
+    side = 1.0 / np.sqrt(d)  # eps = 1
+    small = 0.01 + rng.uniform(0, 0.02, size=(30, d))
+    far = np.full(d, side - 0.03)
+    far[0] += side  # far corner of the next cell along x
+    big = far + rng.uniform(0, 0.02, size=(10000, d))
+    bridge = np.full((1, d), 0.05)
+    bridge[0, 0] = side + 0.015
+    if big_first:  # mirrored: the large cell gets the lower Morton index
+        m = 2 * side
+        small, big, bridge = m - small, m - big, m - bridge
+    X = np.concatenate([small, big, bridge])
+    want = dbscan_o1(X, 1.0, 5)
+    assert np.unique(want[1]).size == 1, "test data must form one cluster"
+    _assert_parity(X, 1.0, 5, mode, f"large cell bridge d={d} big_first={big_first}")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_edge_cases(mode, gpu_lib):
     import torch
 
