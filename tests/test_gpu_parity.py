@@ -212,7 +212,7 @@ def test_determinism(gpu_lib):
 @pytest.mark.parametrize("name", sorted(full_size_cases()))
 def test_full_size_against_oracle_hash(name, mode, gpu_lib):
     case = full_size_cases()[name]
-    X = config_workload(case["config"], case["scale"])[0].X
+    X = config_workload(case["config"], case["scale"])[case.get("instance", 0)].X
     assert len(X) == case["n"]
     core, lab = gpu_dbscan(X, case["eps"], case["min_pts"], mode=mode, tag=name)
     summary = {
