@@ -60,7 +60,7 @@ DB_DEV uint64_t test_children(const TreeView& T, int C, int L, int N, const Quer
   const int ch = N * 64 + lane_id();
   dist = __builtin_inf();
   if (ch < nodes_at(C, L - 1)) {
-    const double bd = box_sqdist<D>(q.lo, q.hi, T.lo[L - 1], T.hi[L - 1], T.cap[L - 1], ch);
+    const double bd = box_sqdist<D>(q.lo, q.hi, T.flo[L - 1], T.fhi[L - 1], T.cap[L - 1], ch);
     if (bd <= q.E2) dist = bd;
   }
   bool ok = dist <= q.E2;

@@ -192,6 +192,27 @@ DB_DEV int decide32(const float (&a)[D], const float (&b)[D], const float (&T)[D
   return acc <= tin ? 1 : (acc > tout ? 0 : 2);
 }
 
+// Lower bound of D(p, q) over p in box [alo, ahi] and q in box [blo, bhi], with
+// the second box given as float32 bounds that contain the float64 box (rounded
+// outwards): the gaps are computed in float64 from the widened bounds, so the
+// result is at most the float64 one below and remains a lower bound.
+template <int D>
+DB_DEV double box_sqdist(const double (&alo)[D], const double (&ahi)[D], const float* blo,
+                         const float* bhi, int stride, int j) {
+#pragma clang fp contract(off)
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double l = (double)blo[(size_t)k * stride + j];
+    const double h = (double)bhi[(size_t)k * stride + j];
+    double t = 0.0;
+    if (alo[k] > h) t = alo[k] - h;
+    else if (l > ahi[k]) t = l - ahi[k];
+    acc = acc + t * t;
+  }
+  return acc;
+}
+
 // Lower bound of D(p, q) over p in box [alo, ahi] and q in box [blo, bhi].
 // Rounding is monotone, so the rounded per-dimension gap is at most |fl(p_k - q_k)|
 // for every such pair, and squares and sums preserve the order: a box distance

@@ -116,6 +116,8 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
     w.tree.cap[l] = (int)cap;
     w.tree.lo[l] = c.take<double>(cap * d);
     w.tree.hi[l] = c.take<double>(cap * d);
+    w.tree.flo[l] = c.take<float>(cap * d);
+    w.tree.fhi[l] = c.take<float>(cap * d);
     w.nroot[l] = l > 0 ? c.take<int32_t>(cap) : nullptr;
   }
   w.coreS = c.take<uint8_t>(n);

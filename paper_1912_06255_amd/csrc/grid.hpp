@@ -46,6 +46,10 @@ constexpr uint32_t kEpochSlots = 16;
 struct TreeView {
   const double* lo[kTreeLevels + 1];  // level 0 = cells, SoA [D][cap]
   const double* hi[kTreeLevels + 1];
+  // float32 copies rounded outwards (lo down, hi up) for the walks: half the bytes,
+  // and a box that contains the float64 one only weakens pruning
+  const float* flo[kTreeLevels + 1];
+  const float* fhi[kTreeLevels + 1];
   int cap[kTreeLevels + 1];
 };
 
@@ -718,6 +722,10 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(Work W, int l) {
   const int cs = W.tree.cap[l - 1];
   double* plo = const_cast<double*>(W.tree.lo[l]);
   double* phi = const_cast<double*>(W.tree.hi[l]);
+  float* cflo = const_cast<float*>(W.tree.flo[l - 1]);
+  float* cfhi = const_cast<float*>(W.tree.fhi[l - 1]);
+  float* pflo = const_cast<float*>(W.tree.flo[l]);
+  float* pfhi = const_cast<float*>(W.tree.fhi[l]);
   const int ps = W.tree.cap[l];
   const int lane = lane_id();
   for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < nnode;
@@ -726,11 +734,19 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(Work W, int l) {
     const bool v = ch < nchild;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
-      const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
+      const double ca = v ? clo[(size_t)k * cs + ch] : __builtin_inf();
+      const double cb = v ? chi[(size_t)k * cs + ch] : -__builtin_inf();
+      if (l == 1 && v) {  // float copies of the cell boxes
+        cflo[(size_t)k * cs + ch] = __double2float_rd(ca);
+        cfhi[(size_t)k * cs + ch] = __double2float_ru(cb);
+      }
+      const double a = wave_min(ca);
+      const double b = wave_max(cb);
       if (lane == 0) {
         plo[(size_t)k * ps + j] = a;
         phi[(size_t)k * ps + j] = b;
+        pflo[(size_t)k * ps + j] = __double2float_rd(a);
+        pfhi[(size_t)k * ps + j] = __double2float_ru(b);
       }
     }
   }
