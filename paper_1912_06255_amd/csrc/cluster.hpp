@@ -575,6 +575,7 @@ struct BcpVisitor {
   DB_DEV void dense_cells(int cb, uint64_t alive, int hr, int s0, int s1) {
     const int lane = lane_id();
     const int n = W->n;
+    const bool chunk_order = W->desc->fine_bits > 0;
     bool fresh = true;  // the roots were just taken by group()
     while (alive) {
       // Components merge while this wave works (other waves link concurrently):
@@ -596,11 +597,14 @@ struct BcpVisitor {
       // Unit chunks farther than eps from h's box are skipped whole.  The chunks
       // are taken in windows of 64 (one per lane); the mask of a unit with a
       // single window is computed once per h, larger units recompute it per window.
+      // Without sub-cell order the points of a cell are in input order, every chunk
+      // box spans nearly the whole cell and the test would only cost a load round.
       auto window_mask = [&](int pc0) {
         const int pcl = pc0 + lane;
         bool sv = false;
         if (pcl < nchk)
-          sv = box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+          sv = !chunk_order ||
+               box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
         return ballot(sv);
       };
       const uint64_t mask0 = nchk <= kWave ? window_mask(0) : 0ull;
