@@ -15,7 +15,8 @@ border and noise points), with these readings where the paper leaves room:
 * a point counts itself (D(p, p) = 0);
 * the id of a cluster is the smallest input index of a core point in it;
 * a border point, which the paper lets belong to several clusters, gets the smallest
-  id among the clusters it belongs to; noise gets -1.
+  id among the clusters it belongs to; noise gets -1.  ``brute.membership`` gives the
+  full set of clusters of every point as well.
 
 Two implementations:
 
@@ -26,5 +27,5 @@ Two implementations:
   provably contain every point within eps.  Pinned to O0 by the tests.
 """
 
-from .brute import dbscan_brute, sqdist_rows  # noqa: F401
+from .brute import dbscan_brute, membership, sqdist_rows  # noqa: F401
 from .o1 import dbscan_o1, o1_available, build_o1  # noqa: F401

@@ -106,6 +106,40 @@ def border_labels(X: np.ndarray, core: np.ndarray, label: np.ndarray, E2: float)
     return out
 
 
+def membership(X, eps: float, min_pts: int):
+    """Every cluster each point belongs to, from the definition (paper, section
+    "Preliminaries"): a core point belongs to its own cluster only; a non-core point
+    belongs to every cluster that has a core point within eps (it can be several:
+    border points do not merge clusters); noise belongs to none.
+
+    Returns CSR arrays in input order: offsets int64[n+1] and ids int32[offsets[n]],
+    the ids of each point ascending.  Cluster ids are those of ``dbscan_brute``.
+    """
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    if X.ndim == 1:
+        X = X[:, None]
+    n = X.shape[0]
+    if n == 0:
+        return np.zeros(1, np.int64), np.zeros(0, np.int32)
+    E2 = float(np.float64(eps) * np.float64(eps))
+    core = neighbour_counts(X, E2) >= min_pts
+    label = core_components(X, core, E2)
+    core_idx = np.flatnonzero(core)
+    sets = [[] for _ in range(n)]
+    for i in core_idx:
+        sets[i] = [int(label[i])]
+    non = np.flatnonzero(~core)
+    if core_idx.size:
+        for s, e in _row_blocks(non.size, core_idx.size):
+            w = _within(sqdist_rows(X, non[s:e], core_idx), E2)
+            for r in range(e - s):
+                sets[non[s + r]] = sorted(set(label[core_idx[w[r]]].tolist()))
+    offsets = np.zeros(n + 1, np.int64)
+    offsets[1:] = np.cumsum([len(t) for t in sets])
+    ids = np.array([v for t in sets for v in t], dtype=np.int32)
+    return offsets, ids
+
+
 def dbscan_brute(X, eps: float, min_pts: int):
     """Exact DBSCAN by definition.  Returns (core uint8[n], cluster id int32[n])."""
     X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))

@@ -37,9 +37,11 @@ GOLDEN_CASES = [
 ]
 
 
-def load_golden(name: str):
+def load_golden(name: str, with_members: bool = False):
+    """Fixture rows "coords | core label [| clusters]"; the optional third field is
+    the full membership (ascending ids, "-" for none)."""
     eps = mp = None
-    X, core, label = [], [], []
+    X, core, label, members = [], [], [], []
     with open(os.path.join(GOLDEN, name)) as f:
         for line in f:
             line = line.strip()
@@ -52,12 +54,19 @@ def load_golden(name: str):
                 elif body.startswith("minpts:"):
                     mp = int(body.split(":", 1)[1])
                 continue
-            coords, out = line.split("|")
+            fields = line.split("|")
+            coords, out = fields[0], fields[1]
             X.append([float(v) for v in coords.split()])
             c, lab = out.split()
             core.append(int(c))
             label.append(int(lab))
-    return np.array(X, dtype=np.float64), eps, mp, np.array(core, np.uint8), np.array(label, np.int32)
+            if len(fields) > 2:
+                m = fields[2].split()
+                members.append([] if m == ["-"] else [int(v) for v in m])
+            else:
+                members.append(None)
+    res = (np.array(X, dtype=np.float64), eps, mp, np.array(core, np.uint8), np.array(label, np.int32))
+    return res + (members,) if with_members else res
 
 
 def load_rounding_pairs():
@@ -106,7 +115,7 @@ def pin_rounding(impl):
     return fails
 
 
-def integer_reference(P, eps_int: int, min_pts: int):
+def integer_reference(P, eps_int: int, min_pts: int, with_members: bool = False):
     """DBSCAN on integer coordinates with exact integer arithmetic.
 
     Reachability between core points is the transitive closure (Warshall) of the
@@ -124,13 +133,17 @@ def integer_reference(P, eps_int: int, min_pts: int):
                     if R[k][j]:
                         R[i][j] = True
     cid = [min(j for j in range(n) if R[i][j]) if core[i] else None for i in range(n)]
-    label = []
+    label, members = [], []
     for i in range(n):
         if core[i]:
             label.append(cid[i])
+            members.append([cid[i]])
         else:
-            ids = [cid[j] for j in range(n) if core[j] and adj[i][j]]
-            label.append(min(ids) if ids else -1)
+            ids = sorted({cid[j] for j in range(n) if core[j] and adj[i][j]})
+            label.append(ids[0] if ids else -1)
+            members.append(ids)
+    if with_members:
+        return members
     return np.array(core, np.uint8), np.array(label, np.int32)
 
 
@@ -148,6 +161,60 @@ def pin_integer_bruteforce(impl, cases: int = 60, seed: int = 7):
         if not (np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])):
             fails.append(f"case {case}: P={P} eps={eps} minPts={mp}")
     return fails
+
+
+def _members_of(offsets, ids):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    ids = np.asarray(ids, dtype=np.int64)
+    return [ids[offsets[i]:offsets[i + 1]].tolist() for i in range(len(offsets) - 1)]
+
+
+def pin_members_golden(impl_members):
+    """Hand-worked memberships in the fixtures that carry them."""
+    fails = []
+    for name in GOLDEN_CASES:
+        X, eps, mp, _, _, members = load_golden(name, with_members=True)
+        if any(m is None for m in members):
+            continue
+        got = _members_of(*impl_members(X, eps, mp))
+        if got != members:
+            fails.append(f"{name}: membership {got} want {members}")
+    return fails
+
+
+def pin_members_integer(impl_members, cases: int = 40, seed: int = 17):
+    """Exact integer transitive closure: every point's full set of clusters.
+
+    Random integer clouds almost never hold a point in two clusters, so each case
+    starts from one of the two hand-worked geometries that do (ex2 in 2D, ex6 scaled
+    by 10 onto an integer line), embedded in d = 1..3 dimensions, moved by a random
+    integer translation, reflected and permuted per axis, with far integer noise and
+    small clusters added and the point order shuffled."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ex2, _, _, _, _ = load_golden("ex2_2d_border_tie.txt")
+    ex6, _, _, _, _ = load_golden("ex6_border_bridge.txt")
+    bases = [(ex2.astype(np.int64), 1, 4), (np.rint(ex6 * 10).astype(np.int64), 10, 4)]
+    fails = []
+    multi = 0
+    for case in range(cases):
+        B, eps, mp = bases[case % 2]
+        d = int(rng.integers(max(1, B.shape[1]), 4))
+        P = np.zeros((B.shape[0], d), dtype=np.int64)
+        P[:, :B.shape[1]] = B
+        P = P[:, rng.permutation(d)] * rng.choice([-1, 1], size=d) + rng.integers(-50, 51, size=d)
+        far = rng.integers(200, 260, size=(int(rng.integers(0, 8)), d)) * rng.choice([-1, 1], size=d)
+        P = np.concatenate([P, far])[rng.permutation(len(P) + len(far))].tolist()
+        want = integer_reference(P, eps, mp, with_members=True)
+        multi += sum(len(m) > 1 for m in want)
+        got = _members_of(*impl_members(np.array(P, dtype=np.float64), float(eps), mp))
+        if got != want:
+            fails.append(f"case {case}: P={P} eps={eps} minPts={mp}: {got} want {want}")
+    if multi == 0:
+        fails.append("no point in two clusters: the cases do not exercise full membership")
+    return fails
+
+
+MEMBER_PINS = {"members_golden": pin_members_golden, "members_integer": pin_members_integer}
 
 
 def _canonical_components(n, edges):
