@@ -236,6 +236,31 @@ int dbscan_tune_save(dbscan_ctx *ctx, const char *path);
 int dbscan_tune_load(dbscan_ctx *ctx, const char *path);
 int dbscan_tune_clear(dbscan_ctx *ctx);
 
+/*
+ * Full cluster membership of the last dbscan() call on this context (paper,
+ * section "Preliminaries": a border point belongs to every cluster that has a
+ * core point within eps; Algorithm 4 before its reduction to one id).  For every
+ * point, in input order: a core point has exactly its cluster id, a border point
+ * every distinct cluster id within eps, noise none; ids ascending.
+ *
+ *   offsets  device int64[n + 1], written: CSR offsets (offsets[0] = 0)
+ *   ids      device int32[ids_cap] or NULL; when not NULL, the ids are written
+ *            at ids[offsets[i] .. offsets[i+1])
+ *   total    host: receives offsets[n]
+ *
+ * Call once with ids == NULL to learn *total, then with ids_cap >= *total.
+ * Uses the state the call left in the context (sorted points, core flags, cell
+ * labels, box tree), so it must follow that dbscan() before any other call on the
+ * context other than dbscan_get_stats / dbscan_membership; after dbscan_batch()
+ * (or before any call) it returns DBSCAN_EINVAL, as it does for ids_cap < *total.
+ * Every decision is the float64 test, whatever the mode of the call.  Returns
+ * DBSCAN_EINTERNAL if a point is within eps of more than 256 distinct clusters
+ * (impossible for d <= 8: core points of different clusters are more than eps
+ * apart, so at most 240 fit within eps of one point).  Synchronises with stream.
+ */
+int dbscan_membership(dbscan_ctx *ctx, int64_t *offsets, int32_t *ids, int64_t ids_cap,
+                      int64_t *total, void *stream);
+
 /* Static description of a return code. */
 const char *dbscan_strerror(int code);
 

@@ -89,6 +89,7 @@ class Tuned(ctypes.Structure):
 _lib = None
 _lock = threading.Lock()
 _ctx: dict[int, ctypes.c_void_p] = {}
+_last_n: dict[int, int] = {}  # n of the last dbscan() call per device (sizes membership output)
 
 
 def load():
@@ -118,11 +119,13 @@ def load():
     lib.dbscan_tune_save.argtypes = [vp, ctypes.c_char_p]
     lib.dbscan_tune_load.argtypes = [vp, ctypes.c_char_p]
     lib.dbscan_tune_clear.argtypes = [vp]
+    lib.dbscan_membership.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
               "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option",
-              "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear"):
+              "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear",
+              "dbscan_membership"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -192,6 +195,7 @@ def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None,
     else:
         core, label = out
     sh = _stream_handle(dev, stream)
+    _last_n[dev] = n
     rc = load().dbscan(
         context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
         ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(label.data_ptr()), sh,
@@ -237,6 +241,29 @@ def tune_load(path: str, device: int = 0) -> None:
 
 def tune_clear(device: int = 0) -> None:
     _check(load().dbscan_tune_clear(context(device)), "dbscan_tune_clear")
+
+
+def membership(device: int = 0, stream=None, ids_cap: int | None = None):
+    """Full cluster membership of the last ``dbscan`` call: ``(offsets int64[n+1],
+    ids int32[total])`` on the device, the ids of point i at
+    ``ids[offsets[i]:offsets[i+1]]``, ascending.  ``ids_cap`` overrides the size of
+    the ids buffer (for tests of the size check)."""
+    import torch
+
+    lib = load()
+    dev = torch.device("cuda", device)
+    n = _last_n.get(device, 0)
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    total = ctypes.c_int64()
+    sh = _stream_handle(device, stream)
+    _check(lib.dbscan_membership(context(device), ctypes.c_void_p(offsets.data_ptr()), None, 0,
+                                 ctypes.byref(total), sh), "dbscan_membership")
+    cap = int(total.value) if ids_cap is None else int(ids_cap)
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    _check(lib.dbscan_membership(context(device), ctypes.c_void_p(offsets.data_ptr()),
+                                 ctypes.c_void_p(ids.data_ptr()), cap, ctypes.byref(total), sh),
+           "dbscan_membership")
+    return offsets, ids[: int(total.value)]
 
 
 def stats(device: int = 0, stream=None, raise_on_error: bool = False) -> dict:

@@ -14,6 +14,7 @@
 
 #include "../../include/dbscan.h"
 #include "cluster.hpp"
+#include "membership.hpp"
 
 using namespace db;
 
@@ -43,6 +44,10 @@ struct dbscan_ctx {
   GridDesc* desc = nullptr;  // lives at the start of scratch, survives growth
   size_t desc_bytes = 0;
   int64_t last_n = 0;
+  // the last dbscan() call, for dbscan_membership()
+  bool last_valid = false;
+  int last_d = 0;
+  Work last_work;
   // tuning options
   int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
   int unit_level = -1;  // -1: automatic (1)
@@ -153,6 +158,7 @@ int grow(dbscan_ctx* ctx, int64_t n, int d) {
     (void)hipFree(ctx->scratch);
   }
   drop_graph(ctx);  // a captured batch refers to the old scratch
+  ctx->last_valid = false;
   ctx->scratch = p;
   ctx->scratch_bytes = need;
   ctx->desc = reinterpret_cast<GridDesc*>(p);
@@ -419,6 +425,36 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
 
 }  // namespace
 
+namespace {
+
+template <int D>
+void member_pass(const Work& W, hipStream_t s, int phase, int64_t* count, const int64_t* offsets,
+                 int32_t* ids, uint32_t* overflow) {
+  k_member<D><<<grid_for(ceil_div(W.n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(
+      W, phase, count, offsets, ids, overflow);
+}
+
+void member_dispatch(int d, const Work& W, hipStream_t s, int phase, int64_t* count,
+                     const int64_t* offsets, int32_t* ids, uint32_t* overflow) {
+  switch (d) {
+#define DB_MEMBER(DD) \
+  case DD:            \
+    member_pass<DD>(W, s, phase, count, offsets, ids, overflow); \
+    break;
+    DB_MEMBER(1)
+    DB_MEMBER(2)
+    DB_MEMBER(3)
+    DB_MEMBER(4)
+    DB_MEMBER(5)
+    DB_MEMBER(6)
+    DB_MEMBER(7)
+    DB_MEMBER(8)
+#undef DB_MEMBER
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 int dbscan_ctx_create(dbscan_ctx** out, int device) {
@@ -487,6 +523,9 @@ int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double 
   W.core_out = core_flags;
   W.label_out = cluster_id;
   ctx->last_n = n;
+  ctx->last_valid = true;
+  ctx->last_d = d;
+  ctx->last_work = W;
   if (ctx->profile && !ctx->events_ready) {
     for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i)
       if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return DBSCAN_EHIP;
@@ -521,6 +560,7 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   if (rc != DBSCAN_OK) return rc;
   if (n == 0) {
     ctx->last_n = 0;
+    ctx->last_valid = true;
     return DBSCAN_OK;
   }
   return run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
@@ -688,9 +728,47 @@ int dbscan_tune_clear(dbscan_ctx* ctx) {
   return DBSCAN_OK;
 }
 
+
+int dbscan_membership(dbscan_ctx* ctx, int64_t* offsets, int32_t* ids, int64_t ids_cap,
+                      int64_t* total, void* stream) {
+  if (!ctx || !offsets || !total || ids_cap < 0) return DBSCAN_EINVAL;
+  if (!ctx->last_valid) return DBSCAN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
+  const int64_t n = ctx->last_n;
+  if (n == 0) {
+    *total = 0;
+    if (hipMemsetAsync(offsets, 0, sizeof(int64_t), s) != hipSuccess) return DBSCAN_EHIP;
+    return hipStreamSynchronize(s) == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+  }
+  const Work& W = ctx->last_work;
+  // the sort buffers are free once the cells are built
+  int64_t* count = reinterpret_cast<int64_t*>(W.keyA);
+  int64_t* tiles = reinterpret_cast<int64_t*>(W.keyB);
+  uint32_t* overflow = W.tilectr + 15;
+  if (hipMemsetAsync(overflow, 0, sizeof(uint32_t), s) != hipSuccess) return DBSCAN_EHIP;
+  member_dispatch(ctx->last_d, W, s, 0, count, nullptr, nullptr, overflow);
+  const int64_t ntiles = ceil_div(n, kScanTile);
+  k_scan_tiles<<<(unsigned)ntiles, kBlock, 0, s>>>(count, n, tiles);
+  k_scan_top<<<1, kBlock, 0, s>>>(tiles, ntiles);
+  k_scan_apply<<<(unsigned)ntiles, kBlock, 0, s>>>(count, n, tiles, offsets);
+  uint32_t ovf = 0;
+  if (hipMemcpyAsync(total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&ovf, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DBSCAN_EHIP;
+  if (ovf) return DBSCAN_EINTERNAL;
+  if (!ids) return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+  if (ids_cap < *total) return DBSCAN_EINVAL;
+  member_dispatch(ctx->last_d, W, s, 1, count, offsets, ids, overflow);
+  if (hipStreamSynchronize(s) != hipSuccess) return DBSCAN_EHIP;
+  return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
 int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, int32_t mode,
                  void* stream) {
   if (!ctx || count < 0 || (count > 0 && !inst)) return DBSCAN_EINVAL;
+  ctx->last_valid = false;
   if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
   int64_t nmax = 0;
   int32_t dmax = 1;
