@@ -69,14 +69,16 @@ DB_DEV uint64_t test_children(const TreeView& T, int C, int L, int N, const Quer
   return ballot(ok);
 }
 
-// Walk the subtree of node `node` at level `level` (1 .. top + 1).
-template <int D, class V>
+// Walk the subtree of node `node` at level `level` (Leaf .. top + 1).  The visitor's
+// group() gets the children (at level Leaf - 1) of each entered node of level Leaf:
+// cells for Leaf = 1.
+template <int D, class V, int Leaf = 1>
 DB_DEV void walk_subtree(const TreeView& T, int C, int level, int node, const Query<D>& q, V& vis,
                          const WalkStack& S) {
   const int lane = lane_id();
   double dist;
   const uint64_t m0 = test_children<D>(T, C, level, node, q, vis, dist);
-  if (level == 1) {
+  if (level == Leaf) {
     if (m0) vis.group(node * 64, m0, dist);
     return;
   }
@@ -107,7 +109,7 @@ DB_DEV void walk_subtree(const TreeView& T, int C, int level, int node, const Qu
     double d2;
     const uint64_t m2 = test_children<D>(T, C, lvl - 1, child, q, vis, d2);
     if (!m2) continue;
-    if (lvl - 1 == 1) {
+    if (lvl - 1 == Leaf) {
       if (vis.group(child * 64, m2, d2)) return;
     } else {
       --lvl;
@@ -139,6 +141,102 @@ DB_DEV void walk(const TreeView& T, int C, const Query<D>& q, V& vis, const Walk
   int cnt[kTreeLevels + 2];
   level_counts(C, cnt);
   walk_subtree<D, V>(T, C, top_level(cnt) + 1, 0, q, vis, S);
+}
+
+// ---------------------------------------------------------------------------
+// Node lists.  For each level-1 node (64 consecutive cells) the level-1 nodes whose
+// box is within reach of its box, from one walk per node that stops at level 1.  A
+// cell's box lies inside its node's box, so every node a walk from the cell would
+// enter is in that list, and a walk from a cell can start from it instead of the
+// root (one round of box tests for the whole list instead of one per tree level).
+// Lists longer than kNodeList are marked -1; walks from their cells start at the
+// root.  Built for d <= 3 only: in higher dimensions most lists overflow (node boxes
+// are loose there) and building them cost more than it saved.
+// ---------------------------------------------------------------------------
+constexpr int kNodeList = 64;
+constexpr int kNodeListMaxD = 3;
+
+struct ListVisitor {
+  static constexpr bool kNearestFirst = false;
+  DB_DEV bool keep_node(int, int) const { return true; }
+  int32_t* list;
+  int len;
+  // m: the level-1 nodes cb .. cb + 63 within reach
+  DB_DEV bool group(int cb, uint64_t m, double) {
+    const int lane = lane_id();
+    const int pos = len + __popcll(m & lanemask_lt());
+    if (((m >> lane) & 1ull) && pos < kNodeList) list[pos] = cb + lane;
+    len += __popcll(m);
+    return len > kNodeList;
+  }
+};
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_node_lists(Work W) {
+  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+  const int C = W.desc->n_cells;
+  const int w = threadIdx.x / kWave;
+  const UnitRange R = xcd_units(nodes_at(C, 1));
+  for (long long u = R.first; u < R.end; u += R.step) {
+    const int G = (int)u;
+    Query<D> q;
+    q.E2 = W.E2;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      q.lo[d] = W.tree.lo[1][(size_t)d * W.tree.cap[1] + G];
+      q.hi[d] = W.tree.hi[1][(size_t)d * W.tree.cap[1] + G];
+    }
+    ListVisitor v{W.nlist + (size_t)G * kNodeList, 0};
+    int cnt[kTreeLevels + 2];
+    level_counts(C, cnt);
+    walk_subtree<D, ListVisitor, 2>(W.tree, C, top_level(cnt) + 1, 0, q, v,
+                                    WalkStack{s_m[w], s_cb[w], nullptr});
+    if (lane_id() == 0) W.nlen[G] = v.len > kNodeList ? -1 : v.len;
+  }
+}
+
+// The walk of cell g from its node's list (or from the root if the list overflowed).
+// It enters the same level-1 nodes as walk(): each listed node's box is tested
+// against the query (one lane per node), then the passing nodes are entered in list
+// order, or nearest first for visitors that ask for it.
+template <int D, class V>
+DB_DEV void walk_from_list(const Work& W, int C, int g, const Query<D>& q, V& vis,
+                           const WalkStack& S) {
+  if constexpr (D > kNodeListMaxD) {
+    walk<D>(W.tree, C, q, vis, S);
+    return;
+  }
+  const int G = g >> 6;
+  const int len = W.nlen[G];
+  if (len < 0) {
+    walk<D>(W.tree, C, q, vis, S);
+    return;
+  }
+  const int lane = lane_id();
+  int node = 0;
+  double dist = __builtin_inf();
+  if (lane < len) {
+    node = W.nlist[(size_t)G * kNodeList + lane];
+    const double bd = box_sqdist<D>(q.lo, q.hi, W.tree.flo[1], W.tree.fhi[1], W.tree.cap[1], node);
+    if (bd <= q.E2) dist = bd;
+  }
+  uint64_t todo = ballot(dist <= q.E2);
+  while (todo) {
+    int j;
+    if constexpr (V::kNearestFirst) {
+      const double dv = ((todo >> lane) & 1ull) ? dist : __builtin_inf();
+      const double mind = wave_min(dv);
+      j = __ffsll((long long)(ballot(dv == mind) & todo)) - 1;
+    } else {
+      j = __ffsll((long long)todo) - 1;
+    }
+    todo &= ~(1ull << j);
+    const int N = __shfl(node, j, kWave);
+    double d2;
+    const uint64_t m2 = test_children<D>(W.tree, C, 1, N, q, vis, d2);
+    if (m2 && vis.group(N * 64, m2, d2)) return;
+  }
 }
 
 
@@ -453,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
         else load_point<D>(W.X, n, ps + lane, v.p);
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk<D>(W.tree, C, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
+      walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
       if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
       v.ctr.flush(W.desc);
     }
@@ -902,7 +1000,10 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     v.prune = round >= 1;
     const int anc_level = round < 0 ? top + 1 : round + 1;
     const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
-    walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
+    if (round < 0 && ulevel == 0)
+      walk_from_list<D>(W, C, g, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
+    else
+      walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
     v.ctr.flush(W.desc);
   }
 }
@@ -1115,7 +1216,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
         else load_point<D>(W.X, n, pos, v.p);
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk<D>(W.tree, C, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
+      walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
       if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
       v.ctr.flush(W.desc);
     }

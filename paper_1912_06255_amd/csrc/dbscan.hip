@@ -125,6 +125,8 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
     w.tree.fhi[l] = c.take<float>(cap * d);
     w.nroot[l] = l > 0 ? c.take<int32_t>(cap) : nullptr;
   }
+  w.nlist = c.take<int32_t>((int64_t)w.tree.cap[1] * 64);
+  w.nlen = c.take<int32_t>(w.tree.cap[1]);
   w.coreS = c.take<uint8_t>(n);
   w.cnt = c.take<int32_t>(n);
   w.coreCount = c.take<int32_t>(n);
@@ -219,6 +221,8 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
     const int64_t nodes = W.tree.cap[l];
     k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
   }
+  if (D <= kNodeListMaxD)
+    k_node_lists<D><<<grid_for(W.tree.cap[1], kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
   if (F32) k_local32<D><<<gp, kBlock, 0, s>>>(W, eps);
   mark(6);
 }

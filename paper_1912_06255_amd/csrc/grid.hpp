@@ -96,6 +96,8 @@ struct Work {
   int32_t* cellLabel; // [n] per cell: cluster id of its core points or -1
   int32_t* cellMin;   // [n] per cell: smallest input index of its core points
   int32_t* nroot[kTreeLevels + 1];  // per tree node (levels 1..): common root or -1/-2
+  int32_t* nlist;     // [cap1][64] level-1 nodes within reach of each level-1 node
+  int32_t* nlen;      // [cap1] list length, -1 when longer than 64
   int32_t* blabel;    // [n] border label, cell order
   int32_t* cnt;       // [n] neighbours within eps, capped at count_cap, cell order
 };
