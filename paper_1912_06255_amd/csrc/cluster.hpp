@@ -390,12 +390,21 @@ DB_DEV bool filtered_hit(const Work* W, bool valid, const float (&ap)[D], const 
 // Per-wave counters of one unit of work, flushed once with stat_add.
 struct Counters {
   unsigned long long bcp = 0, links = 0, rechecks = 0, pairs = 0;
-  DB_DEV void flush(GridDesc* g) const {
+  DB_DEV void add(const Counters& o) {
+    bcp += o.bcp;
+    links += o.links;
+    rechecks += o.rechecks;
+    pairs += o.pairs;
+  }
+  // Once per wave, at the end of a kernel: the wave's totals over all its units,
+  // one atomic per counter (no workgroup barrier: waves that finish early leave).
+  DB_DEV void wave_flush(GridDesc* g) const {
     if (lane_id() == 0) {
-      stat_add(g, kCtrBcp, bcp);
-      stat_add(g, kCtrLinks, links);
-      stat_add(g, kCtrRechecks, rechecks);
-      stat_add(g, kCtrPairs, pairs);
+      const int slot = (int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+      stat_add_slot(g, kCtrBcp, slot, bcp);
+      stat_add_slot(g, kCtrLinks, slot, links);
+      stat_add_slot(g, kCtrRechecks, slot, rechecks);
+      stat_add_slot(g, kCtrPairs, slot, pairs);
     }
   }
 };
@@ -518,6 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
   const int cap = W.count_cap;
+  Counters tot;
   const UnitRange R = xcd_units(C);
   for (long long u = R.first; u < R.end; u += R.step) {
     const int g = (int)u;
@@ -553,9 +563,10 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
       if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
-      v.ctr.flush(W.desc);
+      tot.add(v.ctr);
     }
   }
+  tot.wave_flush(W.desc);
 }
 
 // Core flags of one minPts from the counts (Algorithm 2's test), the number of
@@ -599,11 +610,18 @@ __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
     }
     ncore += cc;
   }
-  if (lane == 0) stat_add(W.desc, kCtrCore, (unsigned long long)ncore);
+  __shared__ unsigned long long s_core[kWavesPerBlock];
+  if (lane == 0) s_core[w] = (unsigned long long)ncore;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) t += s_core[k];
+    stat_add(W.desc, kCtrCore, t);
+  }
 }
 
 __global__ void k_setting_init(Work W) {
-  if (threadIdx.x < kCtrSlots) W.desc->ctr[kCtrCore][threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kCtrSlots; i += blockDim.x) W.desc->ctr[kCtrCore][i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -945,6 +963,7 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
   // alone.  Links are made from the same cell, and a segment that finds its
   // neighbour already joined (by another segment) skips it.
   const int split = W.bcp_split;
+  Counters tot;
   const UnitRange R = xcd_units((long long)C * split);
   for (long long u = R.first; u < R.end; u += R.step) {
     const int g = (int)(u / split);
@@ -1004,8 +1023,9 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
       walk_from_list<D>(W, C, g, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
     else
       walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
-    v.ctr.flush(W.desc);
+    tot.add(v.ctr);
   }
+  tot.wave_flush(W.desc);
 }
 
 // Node roots for pruning: per node, the common root of its core cells, -1 when
@@ -1163,6 +1183,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
+  Counters tot;
   const UnitRange R = xcd_units(C);
   for (long long u = R.first; u < R.end; u += R.step) {
     const int g = (int)u;
@@ -1218,9 +1239,10 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
       if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
-      v.ctr.flush(W.desc);
+      tot.add(v.ctr);
     }
   }
+  tot.wave_flush(W.desc);
 }
 
 // Results back to input order.

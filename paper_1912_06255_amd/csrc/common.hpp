@@ -31,16 +31,20 @@ struct GridDesc {
   int32_t n_unsafe;       // cells whose float64 diameter test failed
   unsigned long long max_extent_bits;  // largest cell extent (float64 bits, >= 0)
   float tin, tout;        // float32 filter thresholds (IN if <= tin, OUT if > tout)
-  // Counters, spread over kCtrSlots addresses (by wave) so that concurrent
+  // Counters, spread over kCtrSlots addresses (by workgroup) so that concurrent
   // updates do not serialise on one address; the host sums the slots.
-  unsigned long long ctr[5][64];
+  unsigned long long ctr[5][256];
 };
 
-constexpr int kCtrSlots = 64;
+constexpr int kCtrSlots = 256;
 enum { kCtrBcp = 0, kCtrLinks = 1, kCtrRechecks = 2, kCtrPairs = 3, kCtrCore = 4 };
 
+DB_DEV void stat_add_slot(GridDesc* g, int which, int slot, unsigned long long v) {
+  if (v) atomicAdd(&g->ctr[which][slot & (kCtrSlots - 1)], v);
+}
+
 DB_DEV void stat_add(GridDesc* g, int which, unsigned long long v) {
-  if (v) atomicAdd(&g->ctr[which][(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCtrSlots - 1)], v);
+  stat_add_slot(g, which, (int)blockIdx.x, v);
 }
 
 // ---------------------------------------------------------------------------
