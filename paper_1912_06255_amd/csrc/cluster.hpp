@@ -575,7 +575,6 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
 __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave, lane = lane_id();
-  int ncore = 0;
   for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
     const int s = W.cellStart[g], e = W.cellStart[g + 1];
     int cc = 0, mn = kIntMax;
@@ -608,21 +607,27 @@ __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
       W.parent[g] = g;
       W.minIdx[g] = kIntMax;
     }
-    ncore += cc;
-  }
-  __shared__ unsigned long long s_core[kWavesPerBlock];
-  if (lane == 0) s_core[w] = (unsigned long long)ncore;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int k = 0; k < kWavesPerBlock; ++k) t += s_core[k];
-    stat_add(W.desc, kCtrCore, t);
   }
 }
 
-__global__ void k_setting_init(Work W) {
-  for (int i = threadIdx.x; i < kCtrSlots; i += blockDim.x) W.desc->ctr[kCtrCore][i] = 0;
+// Number of core points of the last setting, for the statistics (not on the hot
+// path: run when they are read).  One workgroup sums the per-cell core counts.
+__global__ __launch_bounds__(kBlock) void k_core_total(Work W) {
+  __shared__ unsigned long long s_sum[kWavesPerBlock];
+  const int C = W.desc->n_cells;
+  unsigned long long t = 0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) t += (unsigned long long)W.coreCount[c];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, kWave);
+  if (lane_id() == 0) s_sum[threadIdx.x / kWave] = t;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCtrSlots; i += blockDim.x) {
+    unsigned long long v = 0;
+    if (i == 0)
+      for (int k = 0; k < kWavesPerBlock; ++k) v += s_sum[k];
+    W.desc->ctr[kCtrCore][i] = v;
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // ClusterCore (Algorithm 3).  A unit (a core cell, or a tree node whose core

@@ -48,6 +48,9 @@ struct dbscan_ctx {
   bool last_valid = false;
   int last_d = 0;
   Work last_work;
+  // the last setting enqueued (its per-cell core counts give n_core in the stats)
+  bool stats_valid = false;
+  Work stats_work;
   // tuning options
   int bcp_rounds = -1;  // -1: automatic (one pass for d <= 3, rounds above)
   int unit_level = -1;  // -1: automatic (1)
@@ -161,6 +164,7 @@ int grow(dbscan_ctx* ctx, int64_t n, int d) {
   }
   drop_graph(ctx);  // a captured batch refers to the old scratch
   ctx->last_valid = false;
+  ctx->stats_valid = false;
   ctx->scratch = p;
   ctx->scratch_bytes = need;
   ctx->desc = reinterpret_cast<GridDesc*>(p);
@@ -214,13 +218,13 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
   k_cell_safe<D><<<gp, kBlock, 0, s>>>(W);
   // cells that fail the float64 diameter guard become singletons
   k_cells<D><<<tiles, kBlock, 0, s>>>(W, 1);
-  k_cells_copy<<<gp, kBlock, 0, s>>>(W);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 1);
   mark(5);
-  for (int l = 1; l <= kTreeLevels; ++l) {
+  for (int l = 1; l <= 2; ++l) {
     const int64_t nodes = W.tree.cap[l];
     k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
   }
+  k_tree_tail<D><<<1, kBlock, 0, s>>>(W, 3);
   if (D <= kNodeListMaxD)
     k_node_lists<D><<<grid_for(W.tree.cap[1], kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
   if (F32) k_local32<D><<<gp, kBlock, 0, s>>>(W, eps);
@@ -239,7 +243,6 @@ void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds)
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
   const unsigned gb = grid_for(n * W.bcp_split, kWavesPerBlock, 8192);
   const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
-  k_setting_init<<<1, 64, 0, s>>>(W);
   k_core_from_count<<<gw, kBlock, 0, s>>>(W);
   mark(7);
   if (!rounds) {
@@ -384,6 +387,8 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
         Ws.core_out = I.core_flags + (size_t)b * (size_t)I.n;
         Ws.label_out = I.cluster_id + (size_t)b * (size_t)I.n;
         st.setting(Ws, s, none, rounds);
+        ctx->stats_valid = true;
+        ctx->stats_work = Ws;
       }
     }
   }
@@ -530,6 +535,8 @@ int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double 
   ctx->last_valid = true;
   ctx->last_d = d;
   ctx->last_work = W;
+  ctx->stats_valid = true;
+  ctx->stats_work = W;
   if (ctx->profile && !ctx->events_ready) {
     for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i)
       if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return DBSCAN_EHIP;
@@ -826,7 +833,9 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
 int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
   if (!ctx || !out) return DBSCAN_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
-  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DBSCAN_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->stats_valid && ctx->last_n > 0) k_core_total<<<1, kBlock, 0, st>>>(ctx->stats_work);
+  if (hipStreamSynchronize(st) != hipSuccess) return DBSCAN_EHIP;
   GridDesc g;
   if (hipMemcpy(&g, ctx->desc, sizeof(g), hipMemcpyDeviceToHost) != hipSuccess) return DBSCAN_EHIP;
   std::memset(out, 0, sizeof(*out));

@@ -515,15 +515,6 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
 }
 
 // After a split: the second set of cell arrays becomes the first.
-__global__ void k_cells_copy(Work W) {
-  const GridDesc* g = W.desc;
-  if (g->n_unsafe == 0) return;
-  const int n = W.n, C = g->n_cells;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
-    if (i < n) W.cellOf[i] = W.cellOf2[i];
-    if (i <= C) W.cellStart[i] = W.cellStart2[i];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Per-cell float64 point boxes (and the boxes of the aligned 64-point chunks).
@@ -539,6 +530,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
   double* hi = const_cast<double*>(W.tree.hi[0]);
   const int lane = lane_id();
   const int wid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  // after a split the new cells are read from the second arrays, which are also
+  // copied over the first ones here
+  const int32_t* cellOf = only_if_split ? W.cellOf2 : W.cellOf;
+  const int32_t* cellStart = only_if_split ? W.cellStart2 : W.cellStart;
+  if (only_if_split) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+      if (i < n) W.cellOf[i] = W.cellOf2[i];
+      if (i <= C) W.cellStart[i] = W.cellStart2[i];
+    }
+  }
   const int nw = gridDim.x * kWavesPerBlock;
   const int nchunks = (n + kWave - 1) / kWave;
   // (1) Per aligned 64-point chunk: boxes of the cells lying wholly inside it
@@ -547,11 +548,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
     const int base = ch * kWave;
     const int i = base + lane;
     const bool valid = i < n;
-    const int c = valid ? W.cellOf[i] : -1;
-    const int cn = (i + 1 < n && lane < kWave - 1) ? W.cellOf[i + 1] : -2;
+    const int c = valid ? cellOf[i] : -1;
+    const int cn = (i + 1 < n && lane < kWave - 1) ? cellOf[i + 1] : -2;
     const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
     bool owned = false;
-    if (last) owned = W.cellStart[c] >= base && W.cellStart[c + 1] <= base + kWave;
+    if (last) owned = cellStart[c] >= base && cellStart[c + 1] <= base + kWave;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
   // load latencies (and no atomics).
   constexpr int U = D <= 3 ? 8 : 4;
   for (int c = wid; c < C; c += nw) {
-    const int s = W.cellStart[c], e = W.cellStart[c + 1];
+    const int s = cellStart[c], e = cellStart[c + 1];
     if ((s >> 6) == ((e - 1) >> 6)) continue;  // inside one chunk: done in (1)
     double a[D], b[D];
 #pragma unroll
@@ -751,6 +752,43 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(Work W, int l) {
         pfhi[(size_t)k * ps + j] = __double2float_ru(b);
       }
     }
+  }
+}
+
+// Levels l0 .. top in one workgroup (they hold few nodes: C / 64^l0 at most), level
+// after level, instead of one launch each.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
+  const int C = W.desc->n_cells;
+  const int lane = lane_id();
+  for (int l = l0; l <= kTreeLevels; ++l) {
+    const int nchild = level_count(C, l - 1);
+    const int nnode = (nchild + 63) >> 6;
+    const double* clo = W.tree.lo[l - 1];
+    const double* chi = W.tree.hi[l - 1];
+    const int cs = W.tree.cap[l - 1];
+    double* plo = const_cast<double*>(W.tree.lo[l]);
+    double* phi = const_cast<double*>(W.tree.hi[l]);
+    float* pflo = const_cast<float*>(W.tree.flo[l]);
+    float* pfhi = const_cast<float*>(W.tree.fhi[l]);
+    const int ps = W.tree.cap[l];
+    for (int j = threadIdx.x / kWave; j < nnode; j += kWavesPerBlock) {
+      const int ch = j * 64 + lane;
+      const bool v = ch < nchild;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
+        const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
+        if (lane == 0) {
+          plo[(size_t)k * ps + j] = a;
+          phi[(size_t)k * ps + j] = b;
+          pflo[(size_t)k * ps + j] = __double2float_rd(a);
+          pfhi[(size_t)k * ps + j] = __double2float_ru(b);
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
   }
 }
 
