@@ -100,6 +100,7 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   Carver c{base};
   const int64_t tiles = ceil_div(n, kTile);
   w.bbox_part = c.take<double>((int64_t)kBBoxBlocks * 2 * kMaxD);
+  w.bbox_flag = c.take<uint32_t>(kBBoxBlocks);
   w.ghist = c.take<uint32_t>(8 * 256);
   w.tilectr = c.take<uint32_t>(16);
   w.lbstate = c.take<uint64_t>(tiles * 256);
@@ -202,13 +203,11 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
   const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
   const unsigned tiles = (unsigned)ceil_div(n, kTile);
   mark(0);
-  k_init<<<1, kBlock, 0, s>>>(W, first ? 1 : 0);
-  k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W);
-  k_bbox_final<D><<<1, kBlock, 0, s>>>(W, (int)nb);
+  k_bbox_partial<D><<<nb, kBlock, 0, s>>>(W, first ? 1 : 0);
   mark(1);
   // 512 workgroups: each merges its digit histograms into the global ones with
   // one atomic per bin, so fewer, fuller workgroups contend less
-  k_keys<D><<<grid_for(n, kBlock, 512), kBlock, 0, s>>>(W);
+  k_keys<D><<<grid_for(n, kBlock, 512), kBlock, 0, s>>>(W, (int)nb);
   mark(2);
   for (int pass = 0; pass < 8; ++pass) k_sort_pass<<<tiles, kBlock, 0, s>>>(W, pass, (int)tiles);
   mark(3);

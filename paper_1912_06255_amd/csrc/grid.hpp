@@ -70,6 +70,7 @@ struct Work {
 
   GridDesc* desc;
   double* bbox_part;  // [kBBoxBlocks][2*kMaxD]
+  uint32_t* bbox_flag; // [kBBoxBlocks] a non-finite coordinate was seen by that workgroup
   uint32_t* ghist;    // [8][256]
   uint32_t* tilectr;  // [16]
   uint64_t* lbstate;  // [tiles * 256]
@@ -113,7 +114,7 @@ DB_DEV uint32_t epoch_of(const GridDesc* desc, uint32_t slot) {
 // ---------------------------------------------------------------------------
 // `first`: the first grid of a call (or of a batch) also clears the status and the
 // cumulative counters.
-__global__ void k_init(Work W, int first) {
+DB_DEV void init_call(const Work& W, int first) {
   const int t = threadIdx.x;
   for (int i = t; i < 8 * 256; i += blockDim.x) W.ghist[i] = 0;
   if (t < 16) W.tilectr[t] = 0;
@@ -135,8 +136,12 @@ __global__ void k_init(Work W, int first) {
 // Bounding box (partials per block, then one block finalises the grid).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W, int first) {
   __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
+  __shared__ int s_bad;
+  if (blockIdx.x == 0) init_call(W, first);  // nothing below reads what it resets
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
   double lo[D], hi[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
       hi[k] = fmax(hi[k], v);
     }
   }
-  if (bad) atomicOr(&W.desc->status, 1u);
+  if (ballot(bad) && lane_id() == 0) s_bad = 1;
   const int w = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -174,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
     W.bbox_part[blockIdx.x * 2 * kMaxD + k] = a;
     W.bbox_part[blockIdx.x * 2 * kMaxD + kMaxD + k] = b;
   }
+  if (threadIdx.x == 0) W.bbox_flag[blockIdx.x] = (uint32_t)s_bad;
 }
 
 // Grid: origin o = min corner, q_k = floor((x_k - o_k) / s).  The Morton key holds
@@ -181,9 +187,21 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W) {
 // 64 bits; shift = 0 (cells of side s) unless the extent is extreme.  A coarser
 // key only makes cells larger: the diameter guard then splits them into single
 // points, so the result is unchanged.
+struct KeyGrid {
+  double origin[kMaxD];
+  double side;
+  int bits[kMaxD];
+  int total, shift, fine, passes, bad;
+};
+
+// Every workgroup of k_keys reduces the partials and derives the same grid
+// (deterministically); workgroup 0 also publishes it in the descriptor.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_bbox_final(Work W, int nparts) {
+DB_DEV void grid_from_partials(const Work& W, int nparts, KeyGrid& G) {
   __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
   {
     double lo[D], hi[D];
 #pragma unroll
@@ -191,13 +209,16 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(Work W, int nparts) {
       lo[k] = __builtin_inf();
       hi[k] = -__builtin_inf();
     }
+    bool bad = false;
     for (int j = threadIdx.x; j < nparts; j += kBlock) {
+      bad |= W.bbox_flag[j] != 0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         lo[k] = fmin(lo[k], W.bbox_part[j * 2 * kMaxD + k]);
         hi[k] = fmax(hi[k], W.bbox_part[j * 2 * kMaxD + kMaxD + k]);
       }
     }
+    if (ballot(bad) && lane_id() == 0) s_bad = 1;
     const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -209,62 +230,61 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(Work W, int nparts) {
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  GridDesc* g = W.desc;
-  const bool bad = (g->status & 1u) != 0;
-  int len[D];
-  int total = 0;
-  for (int k = 0; k < D; ++k) {
-    double a = s_lo[0][k], b = s_hi[0][k];
-    for (int j = 1; j < kWavesPerBlock; ++j) {
-      a = fmin(a, s_lo[j][k]);
-      b = fmax(b, s_hi[j][k]);
+  if (threadIdx.x == 0) {
+    const bool bad = s_bad != 0 || (W.desc->status & 1u) != 0;
+    int len[D];
+    for (int k = 0; k < D; ++k) {
+      double a = s_lo[0][k], b = s_hi[0][k];
+      for (int j = 1; j < kWavesPerBlock; ++j) {
+        a = fmin(a, s_lo[j][k]);
+        b = fmax(b, s_hi[j][k]);
+      }
+      G.origin[k] = bad ? 0.0 : a;
+      len[k] = 0;
+      if (!bad) {
+        const double qmax = floor((b - a) / W.side);
+        if (!(qmax < 1e308)) len[k] = 1100;          // infinite extent ratio
+        else if (qmax >= 1.0) len[k] = ilogb(qmax) + 1;  // bit length of qmax
+      }
     }
-    g->origin[k] = bad ? 0.0 : a;
-    len[k] = 0;
-    if (!bad) {
-      const double qmax = floor((b - a) / W.side);
-      if (!(qmax < 1e308)) len[k] = 1100;          // infinite extent ratio
-      else if (qmax >= 1.0) len[k] = ilogb(qmax) + 1;  // bit length of qmax
+    int shift = 0, total = 0;
+    for (;;) {
+      int t = 0;
+      for (int k = 0; k < D; ++k) t += max(0, len[k] - shift);
+      if (t <= 64) {
+        total = t;
+        break;
+      }
+      ++shift;
     }
-    total += len[k];
+    for (int k = 0; k < kMaxD; ++k) G.bits[k] = k < D ? max(0, len[k] - shift) : 0;
+    // Sub-cell bits order the points inside each cell along a finer Morton curve, so
+    // that aligned 64-point chunks are spatially compact (tight chunk boxes).
+    int fine = 0;
+    if (shift == 0) fine = max(0, min(W.fine_max, (64 - total) / D));
+    G.side = W.side;
+    G.shift = shift;
+    G.fine = fine;
+    G.total = total + fine * D;
+    G.passes = (total + fine * D + 7) / 8;
+    G.bad = s_bad;
   }
-  int shift = 0;
-  for (;;) {
-    int t = 0;
-    for (int k = 0; k < D; ++k) t += max(0, len[k] - shift);
-    if (t <= 64) {
-      total = t;
-      break;
-    }
-    ++shift;
-  }
-  for (int k = 0; k < kMaxD; ++k) g->bits[k] = k < D ? max(0, len[k] - shift) : 0;
-  // Sub-cell bits order the points inside each cell along a finer Morton curve, so
-  // that aligned 64-point chunks are spatially compact (tight chunk boxes).
-  int fine = 0;
-  if (shift == 0) fine = max(0, min(W.fine_max, (64 - total) / D));
-  g->side = W.side;
-  g->shift = shift;
-  g->fine_bits = fine;
-  g->cell_key_shift = fine * D;
-  g->total_bits = total + fine * D;
-  g->passes = (total + fine * D + 7) / 8;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Morton key of every point and the 8-bit digit histograms of all radix passes.
 // ---------------------------------------------------------------------------
 template <int D>
-DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)[D], int maxb,
+DB_DEV uint64_t morton_key(const double* x, const KeyGrid& g, const int (&bits)[D], int maxb,
                            int fine) {
   unsigned long long c[D];
   unsigned f[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double u = (x[k] - g->origin[k]) / g->side;
+    const double u = (x[k] - g.origin[k]) / g.side;
     const double qc = floor(u);
-    const double q = floor(ldexp(qc, -g->shift));
+    const double q = floor(ldexp(qc, -g.shift));
     const unsigned long long lim = bits[k] >= 64 ? ~0ull : ((1ull << bits[k]) - 1ull);
     unsigned long long v = q > 0.0 ? (unsigned long long)q : 0ull;
     if (!(q < 18446744073709551616.0)) v = lim;
@@ -290,20 +310,34 @@ DB_DEV uint64_t morton_key(const double* x, const GridDesc* g, const int (&bits)
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_keys(Work W) {
+__global__ __launch_bounds__(kBlock) void k_keys(Work W, int nparts) {
   __shared__ uint32_t s_hist[8][256];
+  __shared__ KeyGrid g;
   for (int i = threadIdx.x; i < 8 * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
-  __syncthreads();
-  const GridDesc* g = W.desc;
+  grid_from_partials<D>(W, nparts, g);  // ends with a barrier
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    GridDesc* d = W.desc;
+    for (int k = 0; k < kMaxD; ++k) {
+      d->origin[k] = k < D ? g.origin[k] : 0.0;
+      d->bits[k] = g.bits[k];
+    }
+    d->side = g.side;
+    d->shift = g.shift;
+    d->fine_bits = g.fine;
+    d->cell_key_shift = g.fine * D;
+    d->total_bits = g.total;
+    d->passes = g.passes;
+    if (g.bad) d->status |= 1u;
+  }
   int bits[D];
   int maxb = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    bits[k] = g->bits[k];
+    bits[k] = g.bits[k];
     maxb = max(maxb, bits[k]);
   }
-  const int passes = g->passes;
-  const int fine = g->fine_bits;
+  const int passes = g.passes;
+  const int fine = g.fine;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
     double x[D];
 #pragma unroll
