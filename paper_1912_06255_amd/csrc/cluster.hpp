@@ -13,6 +13,11 @@ constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
 // by cell instead of flattening it.
 constexpr int kDenseGroup = 24;
+// Waves per sparse cell in MarkCore (d <= 3).
+#ifndef DB_MARK_SPLIT
+#define DB_MARK_SPLIT 4
+#endif
+constexpr int kMarkSplit = DB_MARK_SPLIT;
 // Smallest segment of a ClusterCore unit handled by a wave of its own.
 #ifndef DB_BCP_SEGMENT
 #define DB_BCP_SEGMENT 192
@@ -424,8 +429,10 @@ struct MarkCoreVisitor {
   Flat F;
   int* order;        // [64] LDS: group-local cell of each flattened position
   int g, ps, pm;
-  int cnt;           // lane t: count of point ps + t
+  int cnt;           // lane t: count of point ps + t (|g| plus this wave's share)
   uint64_t pending;  // points of the batch still below minPts
+  int split, part;   // this wave tests every split-th candidate chunk, from part
+  int chunk_no;
   double p[D];       // lane t: coordinates of point ps + t (float64 mode)
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
   double ag[D];      // anchor of g (filter mode)
@@ -465,6 +472,7 @@ struct MarkCoreVisitor {
     wave_sync();
     const int tot = flatten_ranges(F, __shfl(cs, src, kWave), __shfl(cn, src, kWave));
     for (int base = 0; base < tot; base += kWave) {
+      if (chunk_no++ % split != part) continue;
       const int k = base + lane;
       const bool valid = k < tot;
       int j = 0, q = 0;
@@ -527,13 +535,19 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int n = W.n;
   const int cap = W.count_cap;
+  // Waves per cell: the candidate chunks of a cell's walk are dealt out to split
+  // waves, which add their counts (cnt is zeroed by k_keys); a wave stops when its
+  // own share reaches the cap, so every count is exact or at least the cap.
+  constexpr int split = D <= 3 ? kMarkSplit : 1;
   Counters tot;
-  const UnitRange R = xcd_units(C);
+  const UnitRange R = xcd_units((long long)C * split);
   for (long long u = R.first; u < R.end; u += R.step) {
-    const int g = (int)u;
+    const int g = (int)(u / split);
+    const int part = (int)(u % split);
     const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
     if (m >= cap) {
-      for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
+      if (part == 0)
+        for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
       continue;
     }
     Query<D> q;
@@ -549,6 +563,9 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       v.pm = min(kWave, e - ps);
       v.cnt = m;
       v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
+      v.split = split;
+      v.part = part;
+      v.chunk_no = 0;
       v.tin = W.desc->tin;
       v.tout = W.desc->tout;
 #pragma unroll
@@ -562,7 +579,10 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
-      if (lane < v.pm) W.cnt[ps + lane] = v.cnt;
+      if (lane < v.pm) {
+        if (split == 1) W.cnt[ps + lane] = v.cnt;
+        else atomicAdd(&W.cnt[ps + lane], part == 0 ? v.cnt : v.cnt - m);
+      }
       tot.add(v.ctr);
     }
   }

@@ -232,7 +232,7 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
 
 template <int D, bool F32>
 void stage_count(const Work& W, hipStream_t s) {
-  k_markcore<D, F32><<<grid_for(W.n, kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
+  k_markcore<D, F32><<<grid_for(W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192), kBlock, 0, s>>>(W);
 }
 
 template <int D, bool F32>

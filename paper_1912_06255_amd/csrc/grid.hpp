@@ -345,6 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(Work W, int nparts) {
     const uint64_t key = morton_key<D>(x, g, bits, maxb, fine);
     W.keyA[i] = key;
     W.idxA[i] = (uint32_t)i;
+    W.cnt[i] = 0;  // MarkCore's waves add their shares to it
     for (int p = 0; p < passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255], 1u);
   }
   __syncthreads();
