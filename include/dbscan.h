@@ -175,8 +175,17 @@ const char *dbscan_phase_name(int32_t phase);
  *   DBSCAN_OPT_UNIT_LEVEL  in rounds, tree nodes up to this level whose core
  *                          cells already form one component are tested as one
  *                          unit (0..5; -1: automatic = 1, the default)
- *   DBSCAN_OPT_FINE_BITS   sub-cell Morton bits per dimension used to order the
- *                          points inside a cell (-1: automatic = 0, else 0..8)
+ *   DBSCAN_OPT_FINE_BITS   sub-cell Morton bits per dimension appended to the
+ *                          sort key, ordering the points inside every cell
+ *                          (-1: automatic = 0, else 0..8)
+ *   DBSCAN_OPT_SUBCELL_MIN with DBSCAN_OPT_FINE_BITS at 0 bits, cells of at
+ *                          least this many points (d <= 3) are put into
+ *                          sub-cell order after the grid is built, the leaves
+ *                          of the paper's per-cell quadtree (section "Range
+ *                          Counting"): MarkCore and ClusterCore then skip or
+ *                          count whole 64-point chunks by their boxes
+ *                          (2..2^31-1; 0: never; -1: automatic = 2048, the
+ *                          default)
  *   DBSCAN_OPT_FORCE_RECHECK  1: the float32 filter sends every pair to the
  *                          float64 recheck (for testing; default 0)
  *   DBSCAN_OPT_BATCH_GRAPH 1: dbscan_batch() captures and replays a HIP graph
@@ -199,6 +208,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_BATCH_GRAPH 5
 #define DBSCAN_OPT_BCP_SPLIT 6
 #define DBSCAN_OPT_FILTER_MAX_D 7
+#define DBSCAN_OPT_SUBCELL_MIN 8
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

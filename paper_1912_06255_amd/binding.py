@@ -24,7 +24,7 @@ ENONFINITE = -4
 EINTERNAL = -5
 
 OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4, "batch_graph": 5,
-           "bcp_split": 6, "filter_max_d": 7}
+           "bcp_split": 6, "filter_max_d": 7, "subcell_min": 8}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1

@@ -8,11 +8,23 @@
 
 namespace db {
 
-constexpr int kIntMax = 0x7fffffff;
 constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
 // by cell instead of flattening it.
 constexpr int kDenseGroup = 24;
+// In sub-cell order, MarkCore takes neighbour cells of at least this many points
+// chunk by chunk with box tests.
+#ifndef DB_LEAF_CELL
+#define DB_LEAF_CELL 128
+#endif
+constexpr int kLeafCell = DB_LEAF_CELL;
+
+// Cells of at least this many points are in sub-cell order (compact 64-point
+// chunks): every cell from kLeafCell points on with sort-time fine bits, the
+// cells k_subsort regrouped otherwise, none when both are off.
+DB_DEV int leaf_min(const Work& W) {
+  return W.desc->fine_bits > 0 ? kLeafCell : max(W.sub_min, kLeafCell);
+}
 // Waves per sparse cell in MarkCore (d <= 3).
 #ifndef DB_MARK_SPLIT
 #define DB_MARK_SPLIT 4
@@ -437,7 +449,69 @@ struct MarkCoreVisitor {
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
   double ag[D];      // anchor of g (filter mode)
   float tin, tout;
+  int lm;            // neighbour cells of at least lm points are taken by chunk boxes
   Counters ctr;
+
+  // A large neighbour cell h in sub-cell order, by its aligned 64-point chunks
+  // (the leaves of the paper's per-cell quadtree): a chunk whose box lies wholly
+  // within eps of a point adds its share of h to that point's count without tests,
+  // a chunk farther than eps is skipped, and only the others are tested.
+  DB_DEV bool leaf_cell(int h, int hs, int he) {
+    const int lane = lane_id();
+    const int n = W->n;
+    float off[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) off[d] = 0.0f;
+    if constexpr (F32) anchor_offsets<D>(W->tree, ag, h, off);
+    for (int ch = hs / kWave; ch <= (he - 1) / kWave; ++ch) {
+      if (chunk_no++ % split != part) continue;
+      const int b0 = max(hs, ch * kWave), b1 = min(he, ch * kWave + kWave);
+      bool test = false;
+      if ((pending >> lane) & 1ull) {
+        if (box_maxdist<D>(p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2)
+          cnt += b1 - b0;
+        else
+          test = box_sqdist<D>(p, p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2;
+      }
+      uint64_t tm = ballot(test);
+      if (tm) {
+        const int q = ch * kWave + lane;
+        const bool valid = q >= b0 && q < b1;
+        double xq[D];
+        float aq[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          xq[d] = 0.0;
+          aq[d] = 0.0f;
+        }
+        if (valid) {
+          if constexpr (F32) load_local<D>(W->X32, n, q, aq);
+          else load_point<D>(W->X, n, q, xq);
+        }
+        while (tm) {
+          const int t = __ffsll((long long)tm) - 1;
+          tm &= tm - 1;
+          bool hit;
+          if constexpr (F32) {
+            float at[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+            hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks);
+          } else {
+            double xp[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
+            hit = valid && sqdist<D>(xp, xq) <= W->E2;
+          }
+          const int add = __popcll(ballot(hit));
+          if (lane == t) cnt += add;
+        }
+      }
+      pending &= ~ballot(cnt >= W->count_cap);
+      if (!pending) return true;
+    }
+    return false;
+  }
 
   DB_DEV bool group(int cb, uint64_t m, double dist) {
     if (g >= cb && g < cb + 64) m &= ~(1ull << (g - cb));
@@ -470,7 +544,17 @@ struct MarkCoreVisitor {
     wave_sync();
     const int src = order[lane];
     wave_sync();
-    const int tot = flatten_ranges(F, __shfl(cs, src, kWave), __shfl(cn, src, kWave));
+    const int rcs = __shfl(cs, src, kWave), rcn = __shfl(cn, src, kWave);
+    bool big = false;
+    if constexpr (D <= 3) {
+      big = rcn >= lm;
+      for (uint64_t bm = ballot(big); bm; bm &= bm - 1) {
+        const int r = __ffsll((long long)bm) - 1;
+        const int hs = bcast(rcs, r);
+        if (leaf_cell(cb + bcast(src, r), hs, hs + bcast(rcn, r))) return true;
+      }
+    }
+    const int tot = flatten_ranges(F, rcs, big ? 0 : rcn);
     for (int base = 0; base < tot; base += kWave) {
       if (chunk_no++ % split != part) continue;
       const int k = base + lane;
@@ -573,9 +657,10 @@ __global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
         v.p[d] = 0.0;
         v.ap[d] = 0.0f;
       }
+      v.lm = D <= 3 ? leaf_min(W) : kIntMax;
       if (lane < v.pm) {
         if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
-        else load_point<D>(W.X, n, ps + lane, v.p);
+        if (!F32 || v.lm != kIntMax) load_point<D>(W.X, n, ps + lane, v.p);
       }
       if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
       walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
@@ -673,6 +758,8 @@ struct BcpVisitor {
   int ucell;       // a core cell of the unit; links are made from it
   int rg;          // a root of the unit's component (refreshed per group; stale is safe)
   Query<D> uq;     // box of the unit
+  double* ub;      // [2 D][64] LDS: the unit's chunk boxes (lo, then hi), when it has <= 64
+  bool ub_ready;
   int excl_level;  // node already covered by an earlier round (level, index), or -1
   int excl_idx;
   bool prune;      // node roots of the previous round are valid
@@ -710,13 +797,150 @@ struct BcpVisitor {
     return uf_find(W->parent, r) != rg;
   }
 
+  // One 64 x 64 tile: the wave's q points of cell h (one per lane) against the
+  // unit's chunk cidx.  Unit points farther than eps from the box [blo, bhi], which
+  // holds every valid q, drop out first.  Links the unit to h at the first pair
+  // within eps and returns true.
+  DB_DEV bool tile(int cidx, int h, const double (&xq)[D], const float (&aq)[D], bool valid,
+                   int q, const double (&blo)[D], const double (&bhi)[D]) {
+    const int lane = lane_id();
+    const int chunk = c0 + cidx;
+    double xp[D];
+    float ap[D];
+    int pcell = -1;
+    bool pv = false;
+    load_chunk(cidx, xp, ap, pcell, pv);
+    pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2;
+    uint64_t pm = ballot(pv);
+    int curcell = -1;
+    float off[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) off[d] = 0.0f;
+    while (pm) {
+      const int t = __ffsll((long long)pm) - 1;
+      pm &= pm - 1;
+      bool hit;
+      ctr.pairs += (unsigned long long)__popcll(ballot(valid));
+      if constexpr (F32) {
+        const int pc = bcast(pcell, t);
+        if (pc != curcell) {
+          curcell = pc;
+          double apc[D];
+          load_anchor<D>(W->tree, pc, apc);
+          anchor_offsets<D>(W->tree, apc, h, off);
+        }
+        float at[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+        hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
+                              ctr.rechecks);
+      } else {
+        double xt[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
+        hit = valid && sqdist<D>(xt, xq) <= W->E2;
+      }
+      if (ballot(hit)) {
+        bool linked = false;
+        if (lane == 0) linked = uf_link(W->parent, ucell, h);
+        ctr.links += ballot(linked) ? 1ull : 0ull;
+        return true;
+      }
+    }
+    return false;
+  }
+
+  // Loads the q points of h held by sorted positions [qb, qb + 64) (lane = one
+  // position); a q takes part when it lies in [hs, he), is core and lies within
+  // eps of the unit's box.
+  DB_DEV bool load_q(int qb, int hs, int he, double (&xq)[D], float (&aq)[D], int& q) const {
+    q = qb + lane_id();
+    bool valid = q >= hs && q < he;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      xq[d] = 0.0;
+      aq[d] = 0.0f;
+    }
+    if (valid) {
+      const uint8_t core = W->coreS[q];
+      load_point<D>(W->X, W->n, q, xq);
+      if constexpr (F32) load_local<D>(W->X32, W->n, q, aq);
+      valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
+    }
+    return valid;
+  }
+
+  // Sub-cell order: the points of large cells follow a Morton curve inside the
+  // cell, so every aligned 64-point chunk covers a compact part of it, like a leaf
+  // of the paper's per-cell quadtree.  Chunks of h farther than eps from the
+  // unit's box are skipped unloaded, and each remaining q chunk is tested only
+  // against the unit chunks within eps of the box of its taking-part points: far
+  // corners of two large cells cost box tests, not tiles.  The unit's chunk boxes
+  // sit in LDS when it has at most 64.
+  DB_DEV bool dense_leaves(int h, int hs, int he) {
+    const int lane = lane_id();
+    const int cap = W->chunkCap;
+    const bool ub_lds = nchk <= kWave;
+    if (ub_lds && !ub_ready) {
+      if (lane < nchk) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          ub[k * kWave + lane] = W->chunkLo[(size_t)k * cap + c0 + lane];
+          ub[(D + k) * kWave + lane] = W->chunkHi[(size_t)k * cap + c0 + lane];
+        }
+      }
+      wave_sync();
+      ub_ready = true;
+    }
+    const int hc0 = hs / kWave, hc1 = (he - 1) / kWave;
+    for (int hw = hc0; hw <= hc1; hw += kWave) {
+      const int hcl = hw + lane;
+      double hd = hcl <= hc1 ? box_sqdist<D>(uq.lo, uq.hi, W->chunkLo, W->chunkHi, cap, hcl)
+                             : __builtin_inf();
+      for (uint64_t hm = ballot(hd <= W->E2); hm; hm &= hm - 1) {
+        const int j = __ffsll((long long)hm) - 1;
+        double xq[D];
+        float aq[D];
+        int q;
+        const bool valid = load_q((hw + j) * kWave, hs, he, xq, aq, q);
+        if (!ballot(valid)) continue;
+        // the box of the q points that take part (core, within eps of the unit):
+        // much tighter than the chunk's box, so far fewer unit chunks pass
+        double qlo[D], qhi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          qlo[k] = wave_min(valid ? xq[k] : __builtin_inf());
+          qhi[k] = wave_max(valid ? xq[k] : -__builtin_inf());
+        }
+        if (ub_lds) {
+          const bool sv = lane < nchk &&
+                          box_sqdist<D>(qlo, qhi, ub, ub + D * kWave, kWave, lane) <= W->E2;
+          for (uint64_t sm = ballot(sv); sm; sm &= sm - 1)
+            if (tile(__ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi)) return true;
+        } else {
+          for (int pc0 = 0; pc0 < nchk; pc0 += kWave) {
+            const int pcl = pc0 + lane;
+            const bool sv = pcl < nchk && box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, cap,
+                                                        c0 + pcl) <= W->E2;
+            for (uint64_t sm = ballot(sv); sm; sm &= sm - 1)
+              if (tile(pc0 + __ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi))
+                return true;
+          }
+        }
+      }
+    }
+    return false;
+  }
+
   // Dense groups: the live neighbour cells are taken one at a time; the q side is
   // a contiguous run of the cell's points and the cell's box stands in for the box
-  // of each q chunk, so no chunk search or box reduction is needed.
+  // of each q chunk, so no chunk search or box reduction is needed.  Without
+  // sub-cell order the points of a cell are in input order: every 64-point run
+  // spreads over its whole cell, so the first tiles tried usually hold a pair
+  // within eps when one exists, and chunk boxes would prune nothing.
   DB_DEV void dense_cells(int cb, uint64_t alive, int hr, int s0, int s1) {
     const int lane = lane_id();
-    const int n = W->n;
-    const bool chunk_order = W->desc->fine_bits > 0;
+    const int lm = leaf_min(*W);
     bool fresh = true;  // the roots were just taken by group()
     while (alive) {
       // Components merge while this wave works (other waves link concurrently):
@@ -733,90 +957,20 @@ struct BcpVisitor {
       const int c = __ffsll((long long)alive) - 1;
       const int h = cb + c;
       const int hs = bcast(s0, c), he = bcast(s1, c);
-      Query<D> hb;
-      load_box<D>(W->tree, h, hb);
-      // Unit chunks farther than eps from h's box are skipped whole.  The chunks
-      // are taken in windows of 64 (one per lane); the mask of a unit with a
-      // single window is computed once per h, larger units recompute it per window.
-      // Without sub-cell order the points of a cell are in input order, every chunk
-      // box spans nearly the whole cell and the test would only cost a load round.
-      auto window_mask = [&](int pc0) {
-        const int pcl = pc0 + lane;
-        bool sv = false;
-        if (pcl < nchk)
-          sv = !chunk_order ||
-               box_sqdist<D>(hb.lo, hb.hi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
-        return ballot(sv);
-      };
-      const uint64_t mask0 = nchk <= kWave ? window_mask(0) : 0ull;
       bool linked_h = false;
-      for (int qb = hs; qb < he && !linked_h; qb += kWave) {
-        const int q = qb + lane;
-        bool valid = q < he;
-        double xq[D];
-        float aq[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          xq[d] = 0.0;
-          aq[d] = 0.0f;
-        }
-        if (valid) {
-          const uint8_t core = W->coreS[q];
-          load_point<D>(W->X, n, q, xq);
-          if constexpr (F32) load_local<D>(W->X32, n, q, aq);
-          valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
-        }
-        if (!ballot(valid)) continue;
-        for (int pc0 = 0; pc0 < nchk && !linked_h; pc0 += kWave) {
-          uint64_t sm = nchk <= kWave ? mask0 : window_mask(pc0);
-          while (sm && !linked_h) {
-            const int cidx = pc0 + __ffsll((long long)sm) - 1;
-            sm &= sm - 1;
-            const int chunk = c0 + cidx;
-            double xp[D];
-            float ap[D];
-            int pcell = -1;
-            bool pv = false;
-            load_chunk(cidx, xp, ap, pcell, pv);
-            pv = pv && box_sqdist<D>(xp, xp, hb.lo, hb.hi, 1, 0) <= W->E2;
-            uint64_t pm = ballot(pv);
-            int curcell = -1;
-            float off[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) off[d] = 0.0f;
-            while (pm) {
-              const int t = __ffsll((long long)pm) - 1;
-              pm &= pm - 1;
-              bool hit;
-              ctr.pairs += (unsigned long long)__popcll(ballot(valid));
-              if constexpr (F32) {
-                const int pc = bcast(pcell, t);
-                if (pc != curcell) {
-                  curcell = pc;
-                  double apc[D];
-                  load_anchor<D>(W->tree, pc, apc);
-                  anchor_offsets<D>(W->tree, apc, h, off);
-                }
-                float at[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-                hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
-                                      ctr.rechecks);
-              } else {
-                double xt[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
-                hit = valid && sqdist<D>(xt, xq) <= W->E2;
-              }
-              if (ballot(hit)) {
-                bool linked = false;
-                if (lane == 0) linked = uf_link(W->parent, ucell, h);
-                ctr.links += ballot(linked) ? 1ull : 0ull;
-                linked_h = true;
-                break;
-              }
-            }
-          }
+      if (he - hs >= lm || pe - ps >= lm) {
+        linked_h = dense_leaves(h, hs, he);
+      } else {
+        Query<D> hb;
+        load_box<D>(W->tree, h, hb);
+        for (int qb = hs; qb < he && !linked_h; qb += kWave) {
+          double xq[D];
+          float aq[D];
+          int q;
+          const bool valid = load_q(qb, hs, he, xq, aq, q);
+          if (!ballot(valid)) continue;
+          for (int cidx = 0; cidx < nchk && !linked_h; ++cidx)
+            linked_h = tile(cidx, h, xq, aq, valid, q, hb.lo, hb.hi);
         }
       }
       if (linked_h) {
@@ -976,6 +1130,7 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
   __shared__ int s_start[kWavesPerBlock][kWave];
   __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
   __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+  __shared__ double s_ub[kWavesPerBlock][BcpVisitor<D, F32>::kDensePath ? 2 * D * kWave : 1];
   const int C = W.desc->n_cells;
   int cnt[kTreeLevels + 2];
   level_counts(C, cnt);
@@ -1005,6 +1160,8 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     BcpVisitor<D, F32> v;
     v.W = &W;
     v.F = Flat{s_pref[w], s_start[w]};
+    v.ub = s_ub[w];
+    v.ub_ready = false;
     v.uq.E2 = W.E2;
     v.tin = W.desc->tin;
     v.tout = W.desc->tout;

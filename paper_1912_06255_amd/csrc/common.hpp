@@ -29,6 +29,7 @@ struct GridDesc {
   uint32_t status;        // DBSCAN_STATUS_* bits
   int32_t n_cells;        // C before/after splitting
   int32_t n_unsafe;       // cells whose float64 diameter test failed
+  int32_t n_sub;          // cells queued for sub-cell order (k_cell_safe, k_subsort)
   unsigned long long max_extent_bits;  // largest cell extent (float64 bits, >= 0)
   float tin, tout;        // float32 filter thresholds (IN if <= tin, OUT if > tout)
   // Counters, spread over kCtrSlots addresses (by workgroup) so that concurrent
@@ -233,6 +234,25 @@ DB_DEV double box_sqdist(const double (&alo)[D], const double (&ahi)[D], const d
     double t = 0.0;
     if (alo[k] > h) t = alo[k] - h;
     else if (l > ahi[k]) t = l - ahi[k];
+    acc = acc + t * t;
+  }
+  return acc;
+}
+
+// Upper bound of D(p, q) over q in the box [lo, hi].  Rounding is monotone, so
+// fl(p_k - q_k) lies between fl(p_k - hi_k) and fl(p_k - lo_k) and its magnitude is
+// at most the larger of theirs; squares and sums keep the order, so a bound of at
+// most E2 proves every point of the box within eps of p (the float64 test, exactly).
+template <int D>
+DB_DEV double box_maxdist(const double (&p)[D], const double* lo, const double* hi, int stride,
+                          int j) {
+#pragma clang fp contract(off)
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = fabs(p[k] - lo[(size_t)k * stride + j]);
+    const double b = fabs(p[k] - hi[(size_t)k * stride + j]);
+    const double t = a > b ? a : b;
     acc = acc + t * t;
   }
   return acc;

@@ -26,6 +26,7 @@ struct Resolved {
   int unit_level;  // largest tree level acting as one unit in rounds
   int split;       // most waves per ClusterCore unit
   int fine;        // sub-cell Morton bits per dimension
+  int sub;         // cells of at least this many points get sub-cell order (k_subsort)
 };
 
 // One tuned choice: instances of dimension d, mode and n in [2^lg, 2^(lg+1)).
@@ -59,6 +60,7 @@ struct dbscan_ctx {
   int batch_graph = 1;
   int bcp_split = -1;   // -1: automatic (2 for one pass, 1 with rounds)
   int filter_max_d = -1;  // -1: automatic (3)
+  int subcell_min = -1;   // -1: automatic (kSubMinAuto for d <= 3), 0: never
   // autotuner: choices per (d, mode, size class), used where an option is automatic
   std::vector<TunedEntry> tuned;
   uint32_t tune_gen = 0;
@@ -119,6 +121,7 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   w.cellOf2 = c.take<int32_t>(n);
   w.cellStart2 = c.take<int32_t>(n + 1);
   w.unsafe = c.take<uint8_t>(n);
+  w.sublist = c.take<int32_t>(n / 2 + 1);
   int64_t cap = n;
   for (int l = 0; l <= kTreeLevels; ++l) {
     if (l > 0) cap = ceil_div(cap, 64);
@@ -218,6 +221,8 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
   // cells that fail the float64 diameter guard become singletons
   k_cells<D><<<tiles, kBlock, 0, s>>>(W, 1);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 1);
+  if constexpr (D <= 3)
+    if (W.sub_min != kIntMax) k_subsort<D><<<kSubBlocks, kSubThreads, 0, s>>>(W);
   mark(5);
   for (int l = 1; l <= 2; ++l) {
     const int64_t nodes = W.tree.cap[l];
@@ -319,8 +324,9 @@ const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) 
 // Explicit options win; automatic ones come from the tuned table, else from fixed
 // rules (one pass for d <= 3 with two waves per large unit, rounds above).
 Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
-  Resolved r{d > 3 ? 1 : 0, 1, 0, 0};
+  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, 0};
   if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
+  r.sub = ctx->subcell_min >= 0 ? ctx->subcell_min : kSubMinAuto;
   if (ctx->bcp_rounds >= 0) r.rounds = ctx->bcp_rounds;
   if (ctx->unit_level >= 0) r.unit_level = ctx->unit_level;
   if (ctx->fine_bits >= 0) r.fine = ctx->fine_bits;
@@ -339,6 +345,9 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.pts = points;
   W.desc = ctx->desc;
   W.fine_max = R.fine;
+  // sub-cell order after the grid is built: d <= 3 (where the chunk-box paths
+  // exist) and only without sort-time fine bits
+  W.sub_min = (d <= 3 && R.fine == 0 && R.sub > 0) ? R.sub : kIntMax;
   W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
   W.bcp_split = R.split;
@@ -414,6 +423,7 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->bcp_split);
   put(k, ctx->tune_gen);
   put(k, ctx->filter_max_d);
+  put(k, ctx->subcell_min);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -699,7 +709,7 @@ int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
   int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version == 1 ? DBSCAN_OK
                                                                             : DBSCAN_EINVAL;
   while (rc == DBSCAN_OK) {
-    TunedEntry e;
+    TunedEntry e{};
     double ms = 0.0;
     const int k = std::fscanf(f, "%d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg, &e.r.rounds,
                               &e.r.unit_level, &e.r.split, &e.r.fine, &ms);
@@ -888,6 +898,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value < -1 || value > DBSCAN_MAX_D) return DBSCAN_EINVAL;
       ctx->filter_max_d = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_SUBCELL_MIN:
+      if (value < -1 || value == 1 || value > kIntMax) return DBSCAN_EINVAL;
+      ctx->subcell_min = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -902,6 +916,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_BATCH_GRAPH: *value = ctx->batch_graph; return DBSCAN_OK;
     case DBSCAN_OPT_BCP_SPLIT: *value = ctx->bcp_split; return DBSCAN_OK;
     case DBSCAN_OPT_FILTER_MAX_D: *value = ctx->filter_max_d; return DBSCAN_OK;
+    case DBSCAN_OPT_SUBCELL_MIN: *value = ctx->subcell_min; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

@@ -40,6 +40,14 @@ DB_DEV UnitRange xcd_units(long long total) {
 constexpr int kSortItems = DB_SORT_ITEMS;
 constexpr int kTile = kBlock * kSortItems;  // keys per radix / scan tile
 
+constexpr int kIntMax = 0x7fffffff;
+
+// Sub-cell order after the grid is built (k_subsort): default size threshold,
+// workgroups of the launch, and the most Morton bits (summed over dimensions).
+constexpr int kSubMinAuto = 2048;
+constexpr int kSubBlocks = 256;
+constexpr int kSubMaxBits = 12;
+
 // Look-back epoch slots within one call: 0..7 radix passes, 8..9 cell scans.
 constexpr uint32_t kEpochSlots = 16;
 
@@ -62,6 +70,8 @@ struct Work {
   int force_recheck;  // filter mode: decide every pair in float64
   int count_cap;      // MarkCore counts neighbours up to this value (largest minPts of the eps)
   int bcp_split;      // waves per ClusterCore unit
+  int sub_min;        // cells of at least this many points get sub-cell order (k_subsort); kIntMax: none
+  int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double E2;
   double side;
   const double* pts;  // input, [n][D]
@@ -127,6 +137,7 @@ DB_DEV void init_call(const Work& W, int first) {
     g->epoch = g->epoch + 1;
     g->n_cells = 0;
     g->n_unsafe = 0;
+    g->n_sub = 0;
     g->max_extent_bits = 0;
     if (first) g->status = 0;
   }
@@ -658,6 +669,167 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) 
   }
 }
 
+// Sub-cell order for large cells: the leaves of the paper's per-cell quadtree
+// (section "Range Counting"), built only where a cell holds at least sub_min
+// points.  The points of the cell's whole aligned 64-point chunks are regrouped
+// by a Morton code over the cell's box, about one code per chunk, so that each
+// chunk covers a compact part of the cell; then those chunks' boxes are computed
+// again.  The partial chunks at the cell's two ends keep their points, so no
+// chunk shared with another cell changes and one workgroup owns each cell (the
+// cells come from the queue k_cell_safe fills; the unsafe-cell split, which only
+// turns unsafe cells into singletons, leaves their points in place).  The
+// order inside one code is arbitrary: no result depends on the order of the
+// points of a cell.  Buffers that are free at this point hold the moved points:
+// the sort's keys and indices, and the float32 coordinates (computed later).
+constexpr int kSubThreads = 1024;
+constexpr int kSubUnroll = 8;
+
+template <int D>
+struct SubCode {
+  double lo[D], sc[D];
+  unsigned top;
+  int f;
+  DB_DEV unsigned operator()(const double (&x)[D]) const {
+    unsigned q[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      // (a NaN from a subnormal extent lands in code 0)
+      const double t = (x[k] - lo[k]) * sc[k];
+      q[k] = t >= (double)top ? top : (t > 0.0 ? (unsigned)t : 0u);
+    }
+    unsigned code = 0;
+    for (int bit = f - 1; bit >= 0; --bit)
+#pragma unroll
+      for (int k = 0; k < D; ++k) code = (code << 1) | ((q[k] >> bit) & 1u);
+    return code;
+  }
+};
+
+template <int D>
+__global__ __launch_bounds__(kSubThreads) void k_subsort(Work W) {
+  static_assert(D <= 3, "sub-cell order is built for d <= 3 only");
+  constexpr int NW = kSubThreads / kWave;
+  constexpr int U = kSubUnroll;
+  __shared__ int s_off[1 << kSubMaxBits];
+  __shared__ uint32_t s_wsum[NW];
+  const GridDesc* g = W.desc;
+  const int nq = g->n_sub, n = W.n;
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  // one float64 array of n per dimension (the float32 coordinates hold
+  // 4 n D >= 8 n bytes for d >= 2) and the moved input indices
+  double* tmp[3] = {reinterpret_cast<double*>(W.keyA), reinterpret_cast<double*>(W.keyB),
+                    reinterpret_cast<double*>(W.X32)};
+  int32_t* tperm = reinterpret_cast<int32_t*>(W.idxA);
+  for (int t = blockIdx.x; t < nq; t += gridDim.x) {
+    const int s = W.sublist[t];
+    const int c = W.cellOf[s];
+    const int e = W.cellStart[c + 1];
+    const int a = (s + kWave - 1) / kWave * kWave, b = e / kWave * kWave;
+    // f bits per dimension: about one Morton code per chunk
+    const int nck = (b - a) / kWave;
+    int lg = 0;
+    while ((1 << lg) < nck) ++lg;
+    SubCode<D> code;
+    code.f = max(1, min((lg + D - 1) / D, kSubMaxBits / D));
+    code.top = (1u << code.f) - 1u;
+    const int B = 1 << (code.f * D);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      code.lo[k] = W.tree.lo[0][(size_t)k * n + c];
+      const double ext = W.tree.hi[0][(size_t)k * n + c] - code.lo[k];
+      code.sc[k] = ext > 0.0 ? ldexp(1.0, code.f) / ext : 0.0;
+    }
+    for (int j = tid; j < B; j += kSubThreads) s_off[j] = 0;
+    __syncthreads();
+    // (1) points per code
+    for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
+      double x[U][D];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kSubThreads;
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[u][k] = i < b ? W.X[(size_t)k * n + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kSubThreads < b) atomicAdd(&s_off[code(x[u])], 1);
+    }
+    __syncthreads();
+    // (2) first position of each code: exclusive prefix over the codes, each
+    // thread owning a run of B / kSubThreads of them
+    {
+      const int per = (B + kSubThreads - 1) / kSubThreads;
+      const int j0 = min(B, tid * per), j1 = min(B, j0 + per);
+      int run = 0;
+      for (int j = j0; j < j1; ++j) run += s_off[j];
+      const int incl = wave_incl_scan(run);
+      if (lane == kWave - 1) s_wsum[w] = (uint32_t)incl;
+      __syncthreads();
+      int pre = a + incl - run;
+      for (int k = 0; k < w; ++k) pre += (int)s_wsum[k];
+      for (int j = j0; j < j1; ++j) {
+        const int v = s_off[j];
+        s_off[j] = pre;
+        pre += v;
+      }
+    }
+    __syncthreads();
+    // (3) every point and its input index to its place in the temporaries
+    for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
+      int pm[U];
+      double x[U][D];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kSubThreads;
+        const bool ok = i < b;
+        pm[u] = ok ? W.perm[i] : 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[u][k] = ok ? W.X[(size_t)k * n + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (i0 + u * kSubThreads >= b) continue;
+        const int t = atomicAdd(&s_off[code(x[u])], 1);
+        tperm[t] = pm[u];
+#pragma unroll
+        for (int k = 0; k < D; ++k) tmp[k][t] = x[u][k];
+      }
+    }
+    __syncthreads();
+    // (4) back into place, one wave per chunk, with the chunk's new box
+    constexpr int V = 4;
+    for (int ch0 = a / kWave + w * V; ch0 < b / kWave; ch0 += NW * V) {
+      int pm[V];
+      double x[V][D];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int i = (ch0 + v) * kWave + lane;
+        const bool ok = i < b;
+        pm[v] = ok ? tperm[i] : 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[v][k] = ok ? tmp[k][i] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int ch = ch0 + v;
+        if (ch * kWave >= b) continue;
+        const int i = ch * kWave + lane;
+        W.perm[i] = pm[v];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          W.X[(size_t)k * n + i] = x[v][k];
+          const double mn = wave_min(x[v][k]), mx = wave_max(x[v][k]);
+          if (lane == 0) {
+            W.chunkLo[(size_t)k * W.chunkCap + ch] = mn;
+            W.chunkHi[(size_t)k * W.chunkCap + ch] = mx;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Diameter guard: D(lo, hi) <= E2 proves every pair in the cell is within eps
 // (monotone rounding; see box_sqdist).  The paper's claim that all points of a
 // cell are within eps holds in exact arithmetic only.
@@ -677,6 +849,14 @@ __global__ void k_cell_safe(Work W) {
     const bool uns = !(sqdist<D>(a, b) <= W.E2);
     W.unsafe[c] = uns;
     bad += uns;
+    // safe cells with at least sub_min points and two whole chunks inside them
+    // are queued for sub-cell order by their first sorted position, which the
+    // split of unsafe cells (into singletons, renumbering the cells) keeps
+    if (!uns && W.sub_min != kIntMax && g->fine_bits == 0) {
+      const int s = W.cellStart[c], e = W.cellStart[c + 1];
+      if (e - s >= W.sub_min && e / kWave - (s + kWave - 1) / kWave >= 2)
+        W.sublist[atomicAdd(&g->n_sub, 1)] = s;
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
   }

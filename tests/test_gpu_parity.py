@@ -117,6 +117,30 @@ def test_unsafe_cells_split(d, eps, mode, gpu_lib):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_unsafe_split_with_sub_cell_order(mode, gpu_lib):
+    """An unsafe cell first in cell order (its split renumbers every later cell)
+    and large cells after it that are put into sub-cell order: the queue of large
+    cells must survive the renumbering."""
+    d, eps = UNSAFE_EPS[0]
+    s = eps / np.sqrt(d)
+    hi = np.nextafter(s, 0.0)
+    rng = np.random.Generator(np.random.PCG64(308))
+    corners = np.concatenate([np.zeros((6, d)), np.full((6, d), hi)])
+    blobs = np.concatenate([rng.uniform(c * eps, c * eps + 1.2 * eps, size=(6000, d))
+                            for c in (20.0, 24.0, 40.0)])
+    far = rng.uniform(60 * eps, 90 * eps, size=(300, d))
+    X = np.concatenate([corners, blobs, far])
+    try:
+        _set_opts(subcell_min=2)
+        (got, st) = gpu_dbscan(X, eps, 10, mode=mode, tag="unsafe + sub-cell", want_stats=True)
+    finally:
+        _set_opts(subcell_min=-1)
+    want = dbscan_o1(X, eps, 10)
+    assert st["n_unsafe"] >= 1, st
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("big_first", [False, True])
 def test_large_cell_bridge(mode, d, big_first, gpu_lib):
@@ -266,6 +290,47 @@ def test_exact_boundaries_4d_lattice(mode, gpu_lib):
     _assert_parity(P, 1.0, 6, mode, "4d lattice")
 
 
+_SUB_RESET = dict(fine_bits=-1, subcell_min=-1)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("eps,mp,opts", [
+    (400.0, 100, dict(fine_bits=2)), (800.0, 1000, dict(fine_bits=2)),
+    (400.0, 400, dict(fine_bits=1)), (400.0, 400, dict(fine_bits=3)),
+    (200.0, 60, dict(fine_bits=2)), (120.0, 30, dict(fine_bits=2)),
+    (400.0, 100, dict(subcell_min=2)), (800.0, 1000, dict(subcell_min=2)),
+    (200.0, 60, dict(subcell_min=2)), (800.0, 300, dict(subcell_min=-1)),
+    (800.0, 300, dict(subcell_min=0))])
+def test_sub_cell_order_large_cells(eps, mp, opts, mode, gpu_lib):
+    """Sub-cell order over cells of hundreds to thousands of points (several walks,
+    5% noise), from sort-time fine bits or regrouped after the grid is built:
+    MarkCore counts whole chunks whose box lies within eps and skips far ones,
+    ClusterCore prunes chunk pairs by their boxes; the labels must not change."""
+    X = seed_spreader_3d(30_000, domain=3e4, restart=0.03, noise_frac=0.05, seed=306)
+    try:
+        _set_opts(**opts)
+        _assert_parity(X, eps, mp, mode, f"sub-cell {opts} eps={eps} mp={mp}")
+    finally:
+        _set_opts(**_SUB_RESET)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("opts", [dict(fine_bits=2), dict(subcell_min=2)])
+def test_sub_cell_order_exact_boundaries(opts, mode, gpu_lib):
+    """Integer lattice with about 60 copies of each site and eps = 3: many pairs and
+    chunk-box corners sit exactly at eps, where a whole chunk may be counted only if
+    every one of its points passes the float64 test.  minPts is above every cell's
+    size, so every count comes from the neighbour walk."""
+    rng = np.random.Generator(np.random.PCG64(307))
+    P = rng.integers(0, 10, size=(60000, 3)).astype(np.float64)
+    try:
+        _set_opts(**opts)
+        for mp in (3000, 5000):
+            _assert_parity(P, 3.0, mp, mode, f"lattice sub-cell {opts} mp={mp}")
+    finally:
+        _set_opts(**_SUB_RESET)
+
+
 @pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
                                   dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
                                   dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=1),
@@ -286,3 +351,21 @@ def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
         _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1)
     assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
     assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
+
+
+def test_option_ranges(gpu_lib):
+    """Out-of-range option values are refused and leave the option unchanged."""
+    from paper_1912_06255_amd import binding
+
+    bad = {"bcp_rounds": [2, -2], "unit_level": [-2, 6], "fine_bits": [-2, 9],
+           "force_recheck": [2], "batch_graph": [-1], "bcp_split": [0, 65],
+           "filter_max_d": [-2, 9], "subcell_min": [-2, 1]}
+    for name, values in bad.items():
+        before = binding.get_option(name)
+        for v in values:
+            with pytest.raises(binding.DbscanError):
+                binding.set_option(name, v)
+            assert binding.get_option(name) == before, name
+    binding.set_option("subcell_min", 2)
+    assert binding.get_option("subcell_min") == 2
+    binding.set_option("subcell_min", -1)
