@@ -877,21 +877,36 @@ struct BcpVisitor {
   // against the unit chunks within eps of the box of its taking-part points: far
   // corners of two large cells cost box tests, not tiles.  The unit's chunk boxes
   // sit in LDS when it has at most 64.
+  // The unit's chunk boxes into LDS, once per unit (units of at most 64 chunks).
+  DB_DEV void ensure_ub() {
+    if (nchk > kWave || ub_ready) return;
+    const int lane = lane_id();
+    if (lane < nchk) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        ub[k * kWave + lane] = W->chunkLo[(size_t)k * W->chunkCap + c0 + lane];
+        ub[(D + k) * kWave + lane] = W->chunkHi[(size_t)k * W->chunkCap + c0 + lane];
+      }
+    }
+    wave_sync();
+    ub_ready = true;
+  }
+
+  // Unit chunks pc0 .. pc0 + 63 whose box lies within eps of [blo, bhi] (one per lane).
+  DB_DEV uint64_t unit_mask(int pc0, const double (&blo)[D], const double (&bhi)[D]) const {
+    const int pcl = pc0 + lane_id();
+    bool sv = false;
+    if (pcl < nchk)
+      sv = (nchk <= kWave ? box_sqdist<D>(blo, bhi, ub, ub + D * kWave, kWave, pcl)
+                          : box_sqdist<D>(blo, bhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl)) <=
+           W->E2;
+    return ballot(sv);
+  }
+
   DB_DEV bool dense_leaves(int h, int hs, int he) {
     const int lane = lane_id();
     const int cap = W->chunkCap;
-    const bool ub_lds = nchk <= kWave;
-    if (ub_lds && !ub_ready) {
-      if (lane < nchk) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          ub[k * kWave + lane] = W->chunkLo[(size_t)k * cap + c0 + lane];
-          ub[(D + k) * kWave + lane] = W->chunkHi[(size_t)k * cap + c0 + lane];
-        }
-      }
-      wave_sync();
-      ub_ready = true;
-    }
+    ensure_ub();
     const int hc0 = hs / kWave, hc1 = (he - 1) / kWave;
     for (int hw = hc0; hw <= hc1; hw += kWave) {
       const int hcl = hw + lane;
@@ -912,21 +927,10 @@ struct BcpVisitor {
           qlo[k] = wave_min(valid ? xq[k] : __builtin_inf());
           qhi[k] = wave_max(valid ? xq[k] : -__builtin_inf());
         }
-        if (ub_lds) {
-          const bool sv = lane < nchk &&
-                          box_sqdist<D>(qlo, qhi, ub, ub + D * kWave, kWave, lane) <= W->E2;
-          for (uint64_t sm = ballot(sv); sm; sm &= sm - 1)
-            if (tile(__ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi)) return true;
-        } else {
-          for (int pc0 = 0; pc0 < nchk; pc0 += kWave) {
-            const int pcl = pc0 + lane;
-            const bool sv = pcl < nchk && box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, cap,
-                                                        c0 + pcl) <= W->E2;
-            for (uint64_t sm = ballot(sv); sm; sm &= sm - 1)
-              if (tile(pc0 + __ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi))
-                return true;
-          }
-        }
+        for (int pc0 = 0; pc0 < nchk; pc0 += kWave)
+          for (uint64_t sm = unit_mask(pc0, qlo, qhi); sm; sm &= sm - 1)
+            if (tile(pc0 + __ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi))
+              return true;
       }
     }
     return false;
@@ -958,6 +962,8 @@ struct BcpVisitor {
       const int h = cb + c;
       const int hs = bcast(s0, c), he = bcast(s1, c);
       bool linked_h = false;
+      // Either side in sub-cell order: chunk boxes prune; both in input order:
+      // every tile samples the whole of both cells.
       if (he - hs >= lm || pe - ps >= lm) {
         linked_h = dense_leaves(h, hs, he);
       } else {
