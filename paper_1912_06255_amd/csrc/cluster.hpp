@@ -35,6 +35,10 @@ constexpr int kMarkSplit = DB_MARK_SPLIT;
 #define DB_BCP_SEGMENT 192
 #endif
 constexpr int kBcpSegment = DB_BCP_SEGMENT;
+// ... and of at least kSegMean times the mean cell size: where most cells are
+// large, cutting all of them only doubles the tests (each segment still meets
+// every neighbour), while cutting the outsize ones shortens the kernel's tail.
+constexpr int kSegMean = 1;
 
 // ---------------------------------------------------------------------------
 // Tree walk.  Every node whose box can hold a point within eps of the query box
@@ -1144,11 +1148,12 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
   if (round > top) return;
   const int w = threadIdx.x / kWave;
   // Up to W.bcp_split waves share one unit: its points are cut into that many
-  // segments of at least kBcpSegment points, and each wave tests its segment
+  // segments of at least seg_min points, and each wave tests its segment
   // against every neighbour, so a large cell no longer sets the kernel's length
   // alone.  Links are made from the same cell, and a segment that finds its
   // neighbour already joined (by another segment) skips it.
   const int split = W.bcp_split;
+  const int seg_min = max(kBcpSegment, (int)((long long)kSegMean * W.n / max(C, 1)));
   Counters tot;
   const UnitRange R = xcd_units((long long)C * split);
   for (long long u = R.first; u < R.end; u += R.step) {
@@ -1193,7 +1198,7 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     }
     {
       const int m = v.pe - v.ps;
-      const int nseg = max(1, min(split, m / kBcpSegment));
+      const int nseg = max(1, min(split, m / seg_min));
       if (part >= nseg) continue;
       const int len = (m + nseg - 1) / nseg;
       v.ps += part * len;
