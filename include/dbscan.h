@@ -215,7 +215,8 @@ int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 
 /*
  * Autotuner over the tuning options (one pass or rounds, the unit level,
- * waves per unit and sub-cell order bits).  dbscan_tune() runs the given
+ * waves per unit, sub-cell order bits and, for d <= 3, the sub-cell threshold
+ * among 2048, 512 and none).  dbscan_tune() runs the given
  * instance with the default options and then changes one option at a time
  * (two sweeps of coordinate descent; a change must be 2% faster), timing each
  * candidate as the median of three runs with HIP events on `stream`.  The best
@@ -227,14 +228,16 @@ int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
  * call synchronises with `stream`.  Returns DBSCAN_EINVAL for n == 0 or bad
  * arguments (as dbscan()), or the first error of a run.
  *
- * dbscan_tune_save() writes the table as text ("dbscan-tune 1", then one line
- * "d mode k rounds unit_level split fine_bits ms" per class);
- * dbscan_tune_load() merges such a file into the table (a malformed file leaves
+ * dbscan_tune_save() writes the table as text ("dbscan-tune 2", then one line
+ * "d mode k rounds unit_level split fine_bits subcell_min ms" per class);
+ * dbscan_tune_load() merges such a file into the table (also the earlier
+ * "dbscan-tune 1" files, whose lines lack subcell_min; a malformed file leaves
  * the table unchanged and returns DBSCAN_EINVAL); dbscan_tune_clear() empties
  * it.  None of the three touches the GPU.
  */
 typedef struct dbscan_tuned {
   int32_t bcp_rounds, unit_level, bcp_split, fine_bits; /* the chosen options */
+  int32_t subcell_min; /* chosen sub-cell threshold (0: none; as DBSCAN_OPT_SUBCELL_MIN) */
   float ms;         /* median time of one call with them */
   float ms_default; /* the same with the default options */
   int32_t trials;   /* option sets timed */

@@ -76,6 +76,7 @@ class Tuned(ctypes.Structure):
         ("unit_level", ctypes.c_int32),
         ("bcp_split", ctypes.c_int32),
         ("fine_bits", ctypes.c_int32),
+        ("subcell_min", ctypes.c_int32),
         ("ms", ctypes.c_float),
         ("ms_default", ctypes.c_float),
         ("trials", ctypes.c_int32),

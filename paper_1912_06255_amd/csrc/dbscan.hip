@@ -26,7 +26,7 @@ struct Resolved {
   int unit_level;  // largest tree level acting as one unit in rounds
   int split;       // most waves per ClusterCore unit
   int fine;        // sub-cell Morton bits per dimension
-  int sub;         // cells of at least this many points get sub-cell order (k_subsort)
+  int sub;         // cells of at least this many points get sub-cell order (k_subsort); 0: none
 };
 
 // One tuned choice: instances of dimension d, mode and n in [2^lg, 2^(lg+1)).
@@ -324,9 +324,9 @@ const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) 
 // Explicit options win; automatic ones come from the tuned table, else from fixed
 // rules (one pass for d <= 3 with two waves per large unit, rounds above).
 Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
-  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, 0};
+  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, kSubMinAuto};
   if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
-  r.sub = ctx->subcell_min >= 0 ? ctx->subcell_min : kSubMinAuto;
+  if (ctx->subcell_min >= 0) r.sub = ctx->subcell_min;
   if (ctx->bcp_rounds >= 0) r.rounds = ctx->bcp_rounds;
   if (ctx->unit_level >= 0) r.unit_level = ctx->unit_level;
   if (ctx->fine_bits >= 0) r.fine = ctx->fine_bits;
@@ -626,7 +626,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     return DBSCAN_EHIP;
   }
   // start from the fixed rules (the tuned table of this class is ignored)
-  Resolved best{d > 3 ? 1 : 0, 1, d > 3 ? 1 : 2, 0};
+  Resolved best{d > 3 ? 1 : 0, 1, d > 3 ? 1 : 2, 0, kSubMinAuto};
   int err = DBSCAN_OK;
   // first run pays one-time costs (scratch growth, code loading); not timed
   rc = run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s, best);
@@ -640,15 +640,21 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
   // coordinate descent over the options, two sweeps; a change must win by 2%
   for (int sweep = 0; sweep < 2 && err == DBSCAN_OK; ++sweep) {
     bool changed = false;
-    for (int opt = 0; opt < 4 && err == DBSCAN_OK; ++opt) {
-      static const int kVals[4][3] = {{0, 1, -1}, {1, 2, 4}, {0, 2, -1}, {0, 1, 2}};
+    for (int opt = 0; opt < 5 && err == DBSCAN_OK; ++opt) {
+      static const int kVals[5][3] = {
+          {0, 1, -1}, {1, 2, 4}, {0, 2, -1}, {0, 1, 2}, {kSubMinAuto, 512, 0}};
       for (int k = 0; k < 3 && err == DBSCAN_OK; ++k) {
         const int v = kVals[opt][k];
         if (v < 0) continue;
         Resolved c = best;
-        int* field = opt == 0 ? &c.rounds : opt == 1 ? &c.split : opt == 2 ? &c.fine : &c.unit_level;
+        int* field = opt == 0 ? &c.rounds
+                     : opt == 1 ? &c.split
+                     : opt == 2 ? &c.fine
+                     : opt == 3 ? &c.unit_level
+                                : &c.sub;
         if (*field == v) continue;
         if (opt == 3 && !c.rounds) continue;  // the unit level only acts in rounds
+        if (opt == 4 && (d > 3 || c.fine > 0)) continue;  // sub-cell order: d <= 3, no fine bits
         *field = v;
         const float t = time_options(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
                                      s, c, e0, e1, &err);
@@ -681,6 +687,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     out->unit_level = best.unit_level;
     out->bcp_split = best.split;
     out->fine_bits = best.fine;
+    out->subcell_min = best.sub;
     out->ms = t_best;
     out->ms_default = t_default;
     out->trials = trials;
@@ -693,10 +700,10 @@ int dbscan_tune_save(dbscan_ctx* ctx, const char* path) {
   if (!ctx || !path) return DBSCAN_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return DBSCAN_EINVAL;
-  std::fprintf(f, "dbscan-tune 1\n");
+  std::fprintf(f, "dbscan-tune 2\n");
   for (const TunedEntry& e : ctx->tuned)
-    std::fprintf(f, "%d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds, e.r.unit_level,
-                 e.r.split, e.r.fine, (double)e.ms);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds,
+                 e.r.unit_level, e.r.split, e.r.fine, e.r.sub, (double)e.ms);
   return std::fclose(f) == 0 ? DBSCAN_OK : DBSCAN_EINVAL;
 }
 
@@ -706,19 +713,28 @@ int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
   if (!f) return DBSCAN_EINVAL;
   int version = 0;
   std::vector<TunedEntry> got;
-  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version == 1 ? DBSCAN_OK
-                                                                            : DBSCAN_EINVAL;
+  // version 1 has no sub-cell threshold (it reads as automatic)
+  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && (version == 1 || version == 2)
+               ? DBSCAN_OK
+               : DBSCAN_EINVAL;
   while (rc == DBSCAN_OK) {
     TunedEntry e{};
+    e.r.sub = kSubMinAuto;
     double ms = 0.0;
-    const int k = std::fscanf(f, "%d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg, &e.r.rounds,
-                              &e.r.unit_level, &e.r.split, &e.r.fine, &ms);
+    const int want = version == 1 ? 8 : 9;
+    const int k = version == 1
+                      ? std::fscanf(f, "%d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg,
+                                    &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine, &ms)
+                      : std::fscanf(f, "%d %d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg,
+                                    &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine,
+                                    &e.r.sub, &ms);
     if (k == EOF) break;
-    const bool ok = k == 8 && e.d >= 1 && e.d <= DBSCAN_MAX_D &&
+    const bool ok = k == want && e.d >= 1 && e.d <= DBSCAN_MAX_D &&
                     (e.mode == DBSCAN_PLAIN_FP64 || e.mode == DBSCAN_FP32_FILTER) &&
                     e.lg >= 0 && e.lg <= 62 && (e.r.rounds == 0 || e.r.rounds == 1) &&
                     e.r.unit_level >= 0 && e.r.unit_level <= kTreeLevels && e.r.split >= 1 &&
-                    e.r.split <= 64 && e.r.fine >= 0 && e.r.fine <= 8;
+                    e.r.split <= 64 && e.r.fine >= 0 && e.r.fine <= 8 && e.r.sub >= 0 &&
+                    e.r.sub != 1;
     if (!ok) {
       rc = DBSCAN_EINVAL;
       break;

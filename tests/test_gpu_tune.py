@@ -34,6 +34,7 @@ def test_tune_then_exact(mode, clean_table):
     res = binding.tune(Xt, 200.0, 10, mode=mode, out=out)
     assert res["bcp_rounds"] in (0, 1) and 0 <= res["unit_level"] <= 5
     assert 1 <= res["bcp_split"] <= 64 and 0 <= res["fine_bits"] <= 8
+    assert res["subcell_min"] in (2048, 512, 0)
     assert res["trials"] >= 4 and res["ms"] > 0 and res["ms"] <= res["ms_default"]
     assert res["size_class"] == int(np.floor(np.log2(n)))
     # the tuning runs leave the instance's exact result
@@ -58,19 +59,29 @@ def test_tune_high_dim_and_table_round_trip(clean_table, tmp_path):
     path = tmp_path / "tune.txt"
     binding.tune_save(str(path))
     lines = path.read_text().splitlines()
-    assert lines[0] == "dbscan-tune 1" and len(lines) == 2
+    assert lines[0] == "dbscan-tune 2" and len(lines) == 2
     f = lines[1].split()
-    assert [int(v) for v in f[:7]] == [5, 0, res["size_class"], res["bcp_rounds"], res["unit_level"],
-                                       res["bcp_split"], res["fine_bits"]]
+    assert [int(v) for v in f[:8]] == [5, 0, res["size_class"], res["bcp_rounds"], res["unit_level"],
+                                       res["bcp_split"], res["fine_bits"], res["subcell_min"]]
     binding.tune_clear()
     binding.tune_save(str(path.with_suffix(".empty")))
-    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 1"]
+    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 2"]
     binding.tune_load(str(path))
     binding.tune_save(str(path.with_suffix(".again")))
     assert path.with_suffix(".again").read_text().splitlines() == lines
 
+    # a version-1 file (no sub-cell threshold) loads, the threshold reading as automatic
+    old = tmp_path / "v1.txt"
+    old.write_text("dbscan-tune 1\n3 1 13 0 1 2 0 1.5\n")
+    binding.tune_clear()
+    binding.tune_load(str(old))
+    binding.tune_save(str(path.with_suffix(".v1")))
+    assert path.with_suffix(".v1").read_text().splitlines() == ["dbscan-tune 2", "3 1 13 0 1 2 0 2048 1.5"]
+    binding.tune_clear()
+    binding.tune_load(str(path))
+
     bad = tmp_path / "bad.txt"
-    bad.write_text("dbscan-tune 1\n5 0 13 1 9 2 0 1.0\n")  # unit level out of range
+    bad.write_text("dbscan-tune 2\n5 0 13 1 9 2 0 2048 1.0\n")  # unit level out of range
     with pytest.raises(binding.DbscanError) as e:
         binding.tune_load(str(bad))
     assert e.value.code == binding.EINVAL
