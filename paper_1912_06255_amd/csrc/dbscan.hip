@@ -237,7 +237,8 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
 
 template <int D, bool F32>
 void stage_count(const Work& W, hipStream_t s) {
-  k_markcore<D, F32><<<grid_for(W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192), kBlock, 0, s>>>(W);
+  k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192),
+                        kBlock, 0, s>>>(W);
 }
 
 template <int D, bool F32>
