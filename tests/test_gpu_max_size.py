@@ -1,6 +1,6 @@
-"""Near the largest supported input: 268 million points (the 16384 x 16384 lattice
-without one column), where every 32-bit position, cell and chunk index is in its
-upper range.  The expected output is the closed form of tests/lattice_case.py
+"""Near the largest supported input: 538 million points (the 23200 x 23200 lattice
+without one column; above 2^29, so n times the four MarkCore waves per cell exceeds
+2^31), where every 32-bit position, cell and chunk index is in its upper range.  The expected output is the closed form of tests/lattice_case.py
 (pinned to the oracle on small lattices by test_lattice_closed_form.py); the oracle
 itself cannot cluster this many points in test time."""
 
@@ -12,8 +12,8 @@ from tests.lattice_case import expected, lattice, points
 
 pytestmark = pytest.mark.gpu
 
-SIDE = 16384
-GAP = 8192
+SIDE = 23200
+GAP = 11600
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +27,7 @@ def case():
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
-def test_lattice_2e28_closed_form(mode, case, gpu_lib):
+def test_lattice_5e8_closed_form(mode, case, gpu_lib):
     X, (want_core, want_label) = case
     (core, label), st = gpu_dbscan(X, 1.0, 5, mode=mode, tag=f"max-size lattice {mode}",
                                    want_stats=True)
