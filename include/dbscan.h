@@ -107,6 +107,25 @@ int dbscan(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d, double e
            void *stream);
 
 /*
+ * Approximate DBSCAN (paper, section "Preliminaries": Gan and Tao's relaxation;
+ * section "Approximate DBSCAN"): as dbscan(), except that two core points whose
+ * distance lies in (eps, eps(1 + rho)] may or may not end up in one cluster.
+ * Core flags are exact; core points within eps always share a cluster; a pair of
+ * core cells is joined only through a pair of core points within eps(1 + rho),
+ * decided as the float64 test D <= fl(R^2), R = fl(eps * fl(1 + rho)); cluster
+ * ids are the smallest core input index of each cluster and non-core points take
+ * the smallest id among clusters with a core point within eps (-1: none), as in
+ * dbscan().  The output need not be unique: any output of this definition is
+ * correct.  rho = 0 gives dbscan()'s result.
+ *   rho         relaxation >= 0 and finite (eps (1 + rho) squared finite)
+ *   (other arguments as for dbscan())
+ * Returns DBSCAN_EINVAL for a bad rho, else as dbscan().
+ */
+int dbscan_approx(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d, double eps,
+                  int32_t min_pts, double rho, int32_t mode, uint8_t *core_flags,
+                  int32_t *cluster_id, void *stream);
+
+/*
  * A batch: many point clouds, each with one or more (eps, minPts) settings
  * (paper, Algorithm 1 run once per cloud and setting).  Results are identical to
  * one dbscan() call per (cloud, setting).

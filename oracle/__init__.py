@@ -25,7 +25,12 @@ Two implementations:
 * ``o1`` (O1): plain C with OpenMP.  Same decisions, but candidates for each range
   query come from the 3^d buckets of side slightly above eps around the point, which
   provably contain every point within eps.  Pinned to O0 by the tests.
+
+For approximate DBSCAN (Gan and Tao's relaxation, also in the preliminaries), whose
+output is not unique, ``approx.check_approx`` checks an output against the relaxed
+definition instead.
 """
 
+from .approx import check_approx, relaxed_e2  # noqa: F401
 from .brute import dbscan_brute, membership, sqdist_rows  # noqa: F401
 from .o1 import dbscan_o1, o1_available, build_o1  # noqa: F401

@@ -108,6 +108,7 @@ def load():
     lib.dbscan_ctx_destroy.argtypes = [vp]
     lib.dbscan_reserve.argtypes = [vp, i64, i32]
     lib.dbscan.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp]
+    lib.dbscan_approx.argtypes = [vp, vp, i64, i32, f64, i32, f64, i32, vp, vp, vp]
     lib.dbscan_get_stats.argtypes = [vp, vp, ctypes.POINTER(Stats)]
     lib.dbscan_batch.argtypes = [vp, ctypes.POINTER(Instance), i32, i32, vp]
     lib.dbscan_set_option.argtypes = [vp, i32, i64]
@@ -126,7 +127,7 @@ def load():
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
               "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option",
               "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear",
-              "dbscan_membership"):
+              "dbscan_membership", "dbscan_approx"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -173,8 +174,11 @@ def _stream_handle(device, stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None, check: bool = True):
-    """Exact DBSCAN of ``points`` (float64 CUDA tensor [n, d]).
+def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None, check: bool = True,
+           rho: float | None = None):
+    """Exact DBSCAN of ``points`` (float64 CUDA tensor [n, d]); with ``rho``,
+    approximate DBSCAN (``dbscan_approx``: core points between eps and eps(1 + rho)
+    apart may or may not share a cluster).
 
     Returns ``(core uint8[n], cluster_id int32[n])`` on the same device.  With
     ``check`` the stream is synchronised and device-detected errors raise
@@ -197,11 +201,17 @@ def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None,
         core, label = out
     sh = _stream_handle(dev, stream)
     _last_n[dev] = n
-    rc = load().dbscan(
-        context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
-        ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(label.data_ptr()), sh,
-    )
-    _check(rc, "dbscan")
+    if rho is None:
+        rc = load().dbscan(
+            context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
+            ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(label.data_ptr()), sh,
+        )
+    else:
+        rc = load().dbscan_approx(
+            context(dev), ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts),
+            float(rho), m, ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(label.data_ptr()), sh,
+        )
+    _check(rc, "dbscan" if rho is None else "dbscan_approx")
     if check and n > 0:
         stats(dev, stream, raise_on_error=True)
     return core, label

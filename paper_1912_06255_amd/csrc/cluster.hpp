@@ -385,24 +385,27 @@ DB_DEV void anchor_offsets(const TreeView& T, const double (&ag)[D], int h, floa
 }
 
 template <int D>
-DB_DEV bool recheck64(const Work* W, int pi, int qi) {
+DB_DEV bool recheck64(const Work* W, int pi, int qi, double e2) {
   double a[D], b[D];
   load_point<D>(W->X, W->n, pi, a);
   load_point<D>(W->X, W->n, qi, b);
-  return sqdist<D>(a, b) <= W->E2;
+  return sqdist<D>(a, b) <= e2;
 }
 
 // One pair per lane in filter mode: p (index pi, coordinates ap) broadcast, q per
-// lane.  Returns whether q is within eps of p; band lanes are rechecked.
+// lane.  Returns whether q is within eps of p; band lanes are rechecked in float64
+// against e2 (E2; ClusterCore passes its own threshold E2b >= E2: a pair the filter
+// proves within eps links either way, one it proves beyond eps never does, which
+// approximate DBSCAN allows).
 template <int D>
 DB_DEV bool filtered_hit(const Work* W, bool valid, const float (&ap)[D], const float (&aq)[D],
                          const float (&off)[D], float tin, float tout, int pi, int qi,
-                         unsigned long long& rechecks) {
+                         unsigned long long& rechecks, double e2) {
   const int cls = valid ? decide32<D>(ap, aq, off, tin, tout) : 0;
   bool hit = cls == 1;
   const uint64_t bm = ballot(cls == 2);
   if (bm) {
-    if (cls == 2) hit = recheck64<D>(W, pi, qi);
+    if (cls == 2) hit = recheck64<D>(W, pi, qi, e2);
     rechecks += (unsigned long long)__popcll(bm);
   }
   return hit;
@@ -500,7 +503,8 @@ struct MarkCoreVisitor {
             float at[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-            hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks);
+            hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks,
+                                  W->E2);
           } else {
             double xp[D];
 #pragma unroll
@@ -590,7 +594,8 @@ struct MarkCoreVisitor {
           float at[D];
 #pragma unroll
           for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks);
+          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks,
+                                  W->E2);
         } else {
           double xp[D];
 #pragma unroll
@@ -814,7 +819,7 @@ struct BcpVisitor {
     int pcell = -1;
     bool pv = false;
     load_chunk(cidx, xp, ap, pcell, pv);
-    pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2;
+    pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2b;
     uint64_t pm = ballot(pv);
     int curcell = -1;
     float off[D];
@@ -837,12 +842,12 @@ struct BcpVisitor {
 #pragma unroll
         for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
         hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
-                              ctr.rechecks);
+                              ctr.rechecks, W->E2b);
       } else {
         double xt[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
-        hit = valid && sqdist<D>(xt, xq) <= W->E2;
+        hit = valid && sqdist<D>(xt, xq) <= W->E2b;
       }
       if (ballot(hit)) {
         bool linked = false;
@@ -869,7 +874,7 @@ struct BcpVisitor {
       const uint8_t core = W->coreS[q];
       load_point<D>(W->X, W->n, q, xq);
       if constexpr (F32) load_local<D>(W->X32, W->n, q, aq);
-      valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
+      valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
     }
     return valid;
   }
@@ -903,7 +908,7 @@ struct BcpVisitor {
     if (pcl < nchk)
       sv = (nchk <= kWave ? box_sqdist<D>(blo, bhi, ub, ub + D * kWave, kWave, pcl)
                           : box_sqdist<D>(blo, bhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl)) <=
-           W->E2;
+           W->E2b;
     return ballot(sv);
   }
 
@@ -916,7 +921,7 @@ struct BcpVisitor {
       const int hcl = hw + lane;
       double hd = hcl <= hc1 ? box_sqdist<D>(uq.lo, uq.hi, W->chunkLo, W->chunkHi, cap, hcl)
                              : __builtin_inf();
-      for (uint64_t hm = ballot(hd <= W->E2); hm; hm &= hm - 1) {
+      for (uint64_t hm = ballot(hd <= W->E2b); hm; hm &= hm - 1) {
         const int j = __ffsll((long long)hm) - 1;
         double xq[D];
         float aq[D];
@@ -1040,7 +1045,7 @@ struct BcpVisitor {
         if constexpr (F32) load_local<D>(W->X32, n, q, aq);
         // points of h farther than eps from the unit's box drop out
         valid = core != 0 && ((alive >> j) & 1ull) &&
-                box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
+                box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
       }
       if (!ballot(valid)) continue;
       double qlo[D], qhi[D];
@@ -1056,7 +1061,7 @@ struct BcpVisitor {
         const int pcl = pc0 + lane;
         bool sv = false;
         if (pcl < nchk)
-          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
+          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2b;
         uint64_t sm = ballot(sv);
         while (sm && !stop) {
           const int b = __ffsll((long long)sm) - 1;
@@ -1069,7 +1074,7 @@ struct BcpVisitor {
           bool pv = false;
           load_chunk(cidx, xp, ap, pcell, pv);
           // points of the unit farther than eps from this chunk's box drop out
-          pv = pv && box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
+          pv = pv && box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2b;
           uint64_t pm = ballot(pv);
           int curcell = -1;
           float off[D];
@@ -1092,12 +1097,12 @@ struct BcpVisitor {
 #pragma unroll
               for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
               hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, chunk * kWave + t, q,
-                                    ctr.rechecks);
+                                    ctr.rechecks, W->E2b);
             } else {
               double xt[D];
 #pragma unroll
               for (int d = 0; d < D; ++d) xt[d] = bcast(xp[d], t);
-              hit = valid && sqdist<D>(xt, xq) <= W->E2;
+              hit = valid && sqdist<D>(xt, xq) <= W->E2b;
             }
             if (!ballot(hit)) continue;
             uint64_t cells = wave_or(hit ? (1ull << j) : 0ull);
@@ -1173,9 +1178,9 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     v.F = Flat{s_pref[w], s_start[w]};
     v.ub = s_ub[w];
     v.ub_ready = false;
-    v.uq.E2 = W.E2;
-    v.tin = W.desc->tin;
-    v.tout = W.desc->tout;
+    v.uq.E2 = W.E2b;  // ClusterCore's radius (eps, or eps (1 + rho) when approximate)
+    v.tin = W.desc->tinb;
+    v.tout = W.desc->toutb;
     if (ulevel == 0) {
       v.ps = W.cellStart[g];
       v.pe = W.cellStart[g + 1];
@@ -1351,7 +1356,8 @@ struct BorderVisitor {
           float at[D];
 #pragma unroll
           for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-          hit = filtered_hit<D>(W, cand, at, aq, off, tin, tout, bcast(pidx, t), q, ctr.rechecks);
+          hit = filtered_hit<D>(W, cand, at, aq, off, tin, tout, bcast(pidx, t), q, ctr.rechecks,
+                              W->E2);
         } else {
           double xp[D];
 #pragma unroll

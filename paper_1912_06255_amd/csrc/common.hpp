@@ -32,6 +32,7 @@ struct GridDesc {
   int32_t n_sub;          // cells queued for sub-cell order (k_cell_safe, k_subsort)
   unsigned long long max_extent_bits;  // largest cell extent (float64 bits, >= 0)
   float tin, tout;        // float32 filter thresholds (IN if <= tin, OUT if > tout)
+  float tinb, toutb;      // the same for ClusterCore's radius (sqrt(E2b))
   // Counters, spread over kCtrSlots addresses (by workgroup) so that concurrent
   // updates do not serialise on one address; the host sums the slots.
   unsigned long long ctr[5][256];

@@ -342,6 +342,7 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   std::memset(static_cast<void*>(&W), 0, sizeof(W));
   W.n = (int)n;
   W.E2 = eps * eps;
+  W.E2b = W.E2;
   W.side = eps / std::sqrt((double)d);
   W.pts = points;
   W.desc = ctx->desc;
@@ -531,12 +532,17 @@ namespace {
 // One exact DBSCAN with the given options (arguments already checked, n > 0).
 int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
             int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
-            hipStream_t s, const Resolved& R) {
+            hipStream_t s, const Resolved& R, double rho = 0.0) {
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
   int rc = grow(ctx, n, d);
   if (rc != DBSCAN_OK) return rc;
   Work W;
   fill_work(ctx, W, points, n, d, eps, R);
+  if (rho > 0.0) {
+    // approximate DBSCAN: ClusterCore links core points up to R = eps (1 + rho)
+    const double r = eps * (1.0 + rho);
+    W.E2b = r * r;
+  }
   W.count_cap = min_pts;
   W.minPts = min_pts;
   W.core_out = core_flags;
@@ -586,6 +592,22 @@ int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double e
   }
   return run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
                  static_cast<hipStream_t>(stream), resolve(ctx, n, d, mode));
+}
+
+int dbscan_approx(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
+                  int32_t min_pts, double rho, int32_t mode, uint8_t* core_flags,
+                  int32_t* cluster_id, void* stream) {
+  const int rc = check_call(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id);
+  if (rc != DBSCAN_OK) return rc;
+  if (!(rho >= 0.0) || !std::isfinite(rho) || !std::isfinite(eps * (1.0 + rho) * eps * (1.0 + rho)))
+    return DBSCAN_EINVAL;
+  if (n == 0) {
+    ctx->last_n = 0;
+    ctx->last_valid = true;
+    return DBSCAN_OK;
+  }
+  return run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
+                 static_cast<hipStream_t>(stream), resolve(ctx, n, d, mode), rho);
 }
 
 namespace {

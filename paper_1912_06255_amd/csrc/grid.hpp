@@ -73,6 +73,7 @@ struct Work {
   int sub_min;        // cells of at least this many points get sub-cell order (k_subsort); kIntMax: none
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double E2;
+  double E2b;         // ClusterCore's pair test: E2, or fl(R^2), R = fl(eps fl(1 + rho)), for approximate DBSCAN
   double side;
   const double* pts;  // input, [n][D]
   uint8_t* core_out;
@@ -883,8 +884,8 @@ __global__ void k_cell_safe(Work W) {
 // Both are widened by 2^-40 for the rounding of this computation and rounded
 // outwards to float32.  Outside a safe exponent range every pair is rechecked.
 template <int D>
-DB_DEV void thresholds(const Work& W, double eps) {
-  GridDesc* g = W.desc;
+DB_DEV void threshold_pair(const Work& W, double eps, double E2, float& tin_out, float& tout_out) {
+  const GridDesc* g = W.desc;
   const double u = 0x1p-24, v = 0x1p-53;
   const double M = __longlong_as_double((long long)g->max_extent_bits) * (1.0 + 0x1p-40);
   const double gd = D * u / (1.0 - D * u);
@@ -892,7 +893,6 @@ DB_DEV void thresholds(const Work& W, double eps) {
   const double Tm = eps * (1.0 + 0x1p-20) + 2.0 * M;
   const double eta = (1.0 + 0x1p-20) * u * (6.0 * M + 2.0 * Tm);
   const double r = sqrt((double)D) * eta * (1.0 + 0x1p-40);
-  const double E2 = W.E2;
   const double ain = sqrt(E2 / (1.0 + gb)) * (1.0 - 0x1p-40) - r;
   const double aout = sqrt(E2 / (1.0 - gb)) * (1.0 + 0x1p-40) + r;
   double tin = ain > 0.0 ? (1.0 - gd) * ain * ain * (1.0 - 0x1p-40) : -1.0;
@@ -903,8 +903,18 @@ DB_DEV void thresholds(const Work& W, double eps) {
     tin = -__builtin_inf();
     tout = __builtin_inf();
   }
-  g->tin = __double2float_rd(tin);
-  g->tout = __double2float_ru(tout);
+  tin_out = __double2float_rd(tin);
+  tout_out = __double2float_ru(tout);
+}
+
+// The thresholds of eps (MarkCore, ClusterBorder) and of ClusterCore's radius,
+// which differs only for approximate DBSCAN (sqrt(E2b), rounded up, then bounds it).
+template <int D>
+DB_DEV void thresholds(const Work& W, double eps) {
+  GridDesc* g = W.desc;
+  threshold_pair<D>(W, eps, W.E2, g->tin, g->tout);
+  const double epsb = W.E2b == W.E2 ? eps : sqrt(W.E2b) * (1.0 + 0x1p-40);
+  threshold_pair<D>(W, epsb, W.E2b, g->tinb, g->toutb);
 }
 
 // Float32 coordinates relative to the anchor of each point's cell (its box corner);

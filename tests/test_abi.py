@@ -50,6 +50,7 @@ def test_null_arguments_are_rejected_without_touching_a_gpu(lib):
     assert lib.dbscan_get_stats(None, None, ctypes.byref(st)) == binding.EINVAL
     # a NULL context is rejected before any argument or device is looked at
     assert lib.dbscan(None, None, 10, 2, 1.0, 3, 0, None, None, None) == binding.EINVAL
+    assert lib.dbscan_approx(None, None, 10, 2, 1.0, 3, 0.01, 0, None, None, None) == binding.EINVAL
 
 
 def test_stats_struct_matches_header():

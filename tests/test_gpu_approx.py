@@ -1,0 +1,75 @@
+"""Approximate DBSCAN on the GPU (dbscan_approx) against the relaxed definition
+(oracle/approx.py: Gan and Tao's approximate DBSCAN in the paper's preliminaries),
+whose output is not unique: every output must pass the checker, rho = 0 must give
+the exact output, and an approximate clustering can only merge exact clusters."""
+
+import numpy as np
+import pytest
+
+from oracle import check_approx, dbscan_o1
+from tests.gpu_helpers import log
+from workloads import blobs_2d, gaussian_mixture, seed_spreader_3d
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64", "fp32_filter"]
+
+
+def _cases():
+    rng = np.random.Generator(np.random.PCG64(601))
+    n = 15_000
+    yield "blobs", blobs_2d(6000, seed=602), 100.0, 10
+    yield "spreader", seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=603), 200.0, 10
+    yield "mixture5", gaussian_mixture(6000, 5, 10, 1.0, 12.0, 0.05, rng), 2.0, 10
+    yield "lattice", rng.integers(0, 25, size=(8000, 3)).astype(np.float64), 1.0, 4
+
+
+CASES = list(_cases())
+
+
+def _approx(X, eps, mp, rho, mode):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    log(f"approx n={X.shape[0]} d={X.shape[1]} eps={eps} mp={mp} rho={rho} mode={mode}")
+    core, lab = binding.dbscan(torch.from_numpy(X).cuda(), eps, mp, mode=mode, rho=rho)
+    return core.cpu().numpy(), lab.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("rho", [0.01, 0.1, 0.5])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_approx_output_is_valid(case, rho, mode, gpu_lib):
+    name, X, eps, mp = CASES[case]
+    core, lab = _approx(X, eps, mp, rho, mode)
+    fails = check_approx(X, eps, mp, rho, core, lab)
+    assert not fails, f"{name} rho={rho}: {fails}"
+    # approximate clusters are unions of exact ones
+    want = dbscan_o1(X, eps, mp)
+    c = want[0].astype(bool)
+    exact_ids = np.unique(want[1][c]).size
+    got_ids = np.unique(lab[c]).size
+    assert got_ids <= exact_ids
+    log(f"{name} rho={rho} {mode}: {exact_ids} exact clusters, {got_ids} approximate")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_rho_zero_is_exact(case, mode, gpu_lib):
+    name, X, eps, mp = CASES[case]
+    got = _approx(X, eps, mp, 0.0, mode)
+    want = dbscan_o1(X, eps, mp)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), name
+
+
+def test_bad_rho_is_refused(gpu_lib):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    X = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
+    for rho in (-0.1, float("nan"), float("inf"), 1e200):
+        with pytest.raises(binding.DbscanError) as e:
+            binding.dbscan(X, 1.0, 2, rho=rho)
+        assert e.value.code == binding.EINVAL
