@@ -11,7 +11,10 @@ namespace db {
 constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
 // by cell instead of flattening it.
-constexpr int kDenseGroup = 24;
+#ifndef DB_DENSE_GROUP
+#define DB_DENSE_GROUP 8
+#endif
+constexpr int kDenseGroup = DB_DENSE_GROUP;
 // In sub-cell order, MarkCore takes neighbour cells of at least this many points
 // chunk by chunk with box tests.
 #ifndef DB_LEAF_CELL
