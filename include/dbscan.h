@@ -212,8 +212,7 @@ const char *dbscan_phase_name(int32_t phase);
  *   DBSCAN_OPT_BCP_SPLIT   most waves per ClusterCore unit: the unit's points
  *                          are cut into up to this many segments of at least
  *                          192 points and of at least the mean cell size, one
- *                          wave each (1..64; -1: automatic, 2 for one pass and
- *                          1 with rounds; the default)
+ *                          wave each (1..64; -1: automatic = 1, the default)
  *   DBSCAN_OPT_FILTER_MAX_D  DBSCAN_FP32_FILTER calls take their pair decisions
  *                          through the float32 filter only for d up to this
  *                          value; above it they decide in float64 directly

@@ -58,7 +58,7 @@ struct dbscan_ctx {
   int fine_bits = -1;   // -1: automatic (0)
   int force_recheck = 0;
   int batch_graph = 1;
-  int bcp_split = -1;   // -1: automatic (2 for one pass, 1 with rounds)
+  int bcp_split = -1;   // -1: automatic (1)
   int filter_max_d = -1;  // -1: automatic (3)
   int subcell_min = -1;   // -1: automatic (kSubMinAuto for d <= 3), 0: never
   // autotuner: choices per (d, mode, size class), used where an option is automatic
@@ -323,7 +323,7 @@ const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) 
 }
 
 // Explicit options win; automatic ones come from the tuned table, else from fixed
-// rules (one pass for d <= 3 with two waves per large unit, rounds above).
+// rules (one pass for d <= 3, rounds above; one wave per unit).
 Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
   Resolved r{d > 3 ? 1 : 0, 1, 0, 0, kSubMinAuto};
   if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
@@ -332,7 +332,7 @@ Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
   if (ctx->unit_level >= 0) r.unit_level = ctx->unit_level;
   if (ctx->fine_bits >= 0) r.fine = ctx->fine_bits;
   if (ctx->bcp_split > 0) r.split = ctx->bcp_split;
-  if (r.split <= 0) r.split = r.rounds ? 1 : 2;
+  if (r.split <= 0) r.split = 1;
   return r;
 }
 
@@ -649,7 +649,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     return DBSCAN_EHIP;
   }
   // start from the fixed rules (the tuned table of this class is ignored)
-  Resolved best{d > 3 ? 1 : 0, 1, d > 3 ? 1 : 2, 0, kSubMinAuto};
+  Resolved best{d > 3 ? 1 : 0, 1, 1, 0, kSubMinAuto};
   int err = DBSCAN_OK;
   // first run pays one-time costs (scratch growth, code loading); not timed
   rc = run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s, best);
