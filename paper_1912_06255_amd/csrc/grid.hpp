@@ -997,6 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
     float* pflo = const_cast<float*>(W.tree.flo[l]);
     float* pfhi = const_cast<float*>(W.tree.fhi[l]);
     const int ps = W.tree.cap[l];
+    double top_lo[D], top_hi[D];  // the box of node 0 (wave 0, lane 0)
     for (int j = threadIdx.x / kWave; j < nnode; j += kWavesPerBlock) {
       const int ch = j * 64 + lane;
       const bool v = ch < nchild;
@@ -1004,6 +1005,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
       for (int k = 0; k < D; ++k) {
         const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
         const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
+        top_lo[k] = a;
+        top_hi[k] = b;
         if (lane == 0) {
           plo[(size_t)k * ps + j] = a;
           phi[(size_t)k * ps + j] = b;
@@ -1011,6 +1014,23 @@ __global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
           pfhi[(size_t)k * ps + j] = __double2float_ru(b);
         }
       }
+    }
+    if (nnode == 1) {
+      // every level above holds this one node with the same box: written directly,
+      // without a round of loads and reductions per level
+      if (threadIdx.x == 0) {
+        for (int u = l + 1; u <= kTreeLevels; ++u) {
+          const int us = W.tree.cap[u];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const_cast<double*>(W.tree.lo[u])[(size_t)k * us] = top_lo[k];
+            const_cast<double*>(W.tree.hi[u])[(size_t)k * us] = top_hi[k];
+            const_cast<float*>(W.tree.flo[u])[(size_t)k * us] = __double2float_rd(top_lo[k]);
+            const_cast<float*>(W.tree.fhi[u])[(size_t)k * us] = __double2float_ru(top_hi[k]);
+          }
+        }
+      }
+      return;
     }
     __threadfence_block();
     __syncthreads();
