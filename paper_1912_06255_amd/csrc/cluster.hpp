@@ -195,13 +195,14 @@ struct ListVisitor {
   }
 };
 
+// (workgroup bid of the nwg doing this job)
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_node_lists(Work W) {
+DB_DEV void node_lists_part(const Work& W, int nwg, int bid) {
   __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
   __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
   const int C = W.desc->n_cells;
   const int w = threadIdx.x / kWave;
-  const UnitRange R = xcd_units(nodes_at(C, 1));
+  const UnitRange R = xcd_units_of(nodes_at(C, 1), nwg, bid);
   for (long long u = R.first; u < R.end; u += R.step) {
     const int G = (int)u;
     Query<D> q;
@@ -218,6 +219,19 @@ __global__ __launch_bounds__(kBlock) void k_node_lists(Work W) {
                                     WalkStack{s_m[w], s_cb[w], nullptr});
     if (lane_id() == 0) W.nlen[G] = v.len > kNodeList ? -1 : v.len;
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_node_lists(Work W) {
+  node_lists_part<D>(W, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// Node lists and the float32 coordinates in one launch (independent jobs): the
+// first nbl workgroups build the lists, the others convert the coordinates.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_lists_local32(Work W, double eps, int nbl) {
+  if ((int)blockIdx.x < nbl) node_lists_part<D>(W, nbl, (int)blockIdx.x);
+  else local32_part<D>(W, eps, (int)gridDim.x - nbl, (int)blockIdx.x - nbl);
 }
 
 // The walk of cell g from its node's list (or from the root if the list overflowed).

@@ -229,9 +229,13 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
     k_tree_level<D><<<grid_for(nodes, kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
   }
   k_tree_tail<D><<<1, kBlock, 0, s>>>(W, 3);
-  if (D <= kNodeListMaxD)
-    k_node_lists<D><<<grid_for(W.tree.cap[1], kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
-  if (F32) k_local32<D><<<gp, kBlock, 0, s>>>(W, eps);
+  const unsigned gl = grid_for(W.tree.cap[1], kWavesPerBlock, 4096);
+  if (D <= kNodeListMaxD && F32)
+    k_lists_local32<D><<<gl + gp, kBlock, 0, s>>>(W, eps, (int)gl);
+  else if (D <= kNodeListMaxD)
+    k_node_lists<D><<<gl, kBlock, 0, s>>>(W);
+  else if (F32)
+    k_local32<D><<<gp, kBlock, 0, s>>>(W, eps);
   mark(6);
 }
 

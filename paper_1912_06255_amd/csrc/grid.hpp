@@ -22,17 +22,21 @@ struct UnitRange {
   long long first, end, step;
 };
 
-DB_DEV UnitRange xcd_units(long long total) {
-  const int G = (int)gridDim.x;
+// (for G workgroups of which this is number bid: part of a launch shared by two jobs)
+DB_DEV UnitRange xcd_units_of(long long total, int G, int bid) {
   const int X = G < kXcds ? G : kXcds;
-  const int x = (int)blockIdx.x % X;
-  const int r = (int)blockIdx.x / X;
+  const int x = bid % X;
+  const int r = bid / X;
   const int per = (G - x + X - 1) / X;  // workgroups b < G with b mod X == x
   const long long chunk = (total + X - 1) / X;
   const long long b = total < (long long)x * chunk ? total : (long long)x * chunk;
   const long long e = total < b + chunk ? total : b + chunk;
   return UnitRange{b + (long long)r * kWavesPerBlock + (long long)(threadIdx.x / kWave), e,
                    (long long)per * kWavesPerBlock};
+}
+
+DB_DEV UnitRange xcd_units(long long total) {
+  return xcd_units_of(total, (int)gridDim.x, (int)blockIdx.x);
 }
 #ifndef DB_SORT_ITEMS
 #define DB_SORT_ITEMS 16
@@ -919,16 +923,22 @@ DB_DEV void thresholds(const Work& W, double eps) {
 
 // Float32 coordinates relative to the anchor of each point's cell (its box corner);
 // the first thread also sets the thresholds.
+// (workgroup bid of the nwg doing this job)
 template <int D>
-__global__ void k_local32(Work W, double eps) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) thresholds<D>(W, eps);
+DB_DEV void local32_part(const Work& W, double eps, int nwg, int bid) {
+  if (bid == 0 && threadIdx.x == 0) thresholds<D>(W, eps);
   const int n = W.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = bid * blockDim.x + threadIdx.x; i < n; i += nwg * blockDim.x) {
     const int c = W.cellOf[i];
 #pragma unroll
     for (int k = 0; k < D; ++k)
       W.X32[(size_t)k * n + i] = (float)(W.X[(size_t)k * n + i] - W.tree.lo[0][(size_t)k * n + c]);
   }
+}
+
+template <int D>
+__global__ void k_local32(Work W, double eps) {
+  local32_part<D>(W, eps, (int)gridDim.x, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
