@@ -73,3 +73,32 @@ def test_bad_rho_is_refused(gpu_lib):
         with pytest.raises(binding.DbscanError) as e:
             binding.dbscan(X, 1.0, 2, rho=rho)
         assert e.value.code == binding.EINVAL
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("rho", [0.1, 0.5])
+def test_approx_through_sub_cell_order(rho, mode, gpu_lib):
+    """Large cells in sub-cell order, so ClusterCore takes its leaf path (chunk-box
+    pruning at the relaxed radius); the output must still pass the checker."""
+    from paper_1912_06255_amd import binding
+
+    X = seed_spreader_3d(8000, domain=1.5e4, restart=0.03, noise_frac=0.05, seed=604)
+    try:
+        binding.set_option("subcell_min", 2)
+        core, lab = _approx(X, 400.0, 100, rho, mode)
+    finally:
+        binding.set_option("subcell_min", -1)
+    fails = check_approx(X, 400.0, 100, rho, core, lab)
+    assert not fails, fails
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [1, 8])
+def test_approx_extreme_dimensions(d, mode, gpu_lib):
+    rng = np.random.Generator(np.random.PCG64(605 + d))
+    X = gaussian_mixture(3000, d, 6, 1.0, 10.0, 0.05, rng)
+    eps = 0.3 if d == 1 else 2.5
+    for rho in (0.0, 0.3):
+        core, lab = _approx(X, eps, 8, rho, mode)
+        fails = check_approx(X, eps, 8, rho, core, lab)
+        assert not fails, f"d={d} rho={rho}: {fails}"
