@@ -5,18 +5,25 @@
 
 A step is one full exact DBSCAN (grid, sort, cell boxes and guard, box tree,
 MarkCore, ClusterCore, relabel, ClusterBorder, scatter) of every (cloud, setting)
-of the workload, inputs already resident in HBM and outputs left in HBM.  Three
-timed legs run the same workload:
+of the workload, inputs already resident in HBM and outputs left in HBM.  The
+default workload is the batched parameter sweep: one 3D seed-spreader cloud of
+10,000,000 points with 16 (eps, minPts) settings.  Four timed legs run it:
 
-  plain    : one dbscan() call per (cloud, setting), float64 decisions;
-  filter   : the same calls with the float32 filter and float64 recheck;
-  batched  : dbscan_batch() with the float32 filter, replaying one captured HIP
-             graph per step (the headline value).
+  plain          : one dbscan() call per (cloud, setting), float64 decisions;
+  filter         : the same calls with the float32 filter and float64 recheck;
+  batched_fp64   : dbscan_batch() in float64, replaying one captured HIP graph;
+  batched        : dbscan_batch() with the float32 filter, replaying one captured
+                   HIP graph per step (the headline value).
 
 Each leg runs W untimed warm-up steps and then exactly K steps between device
-synchronisations; value = points * K / seconds.  A profiled loop of the filter leg
-records per-phase HIP events on the library's stream; the dominant phase gives the
-roofline entry.  The CPU oracle is timed on the host cores on the same workload.
+synchronisations; value = points * K / seconds.  A profiled step of the batched
+filter leg (run eagerly, HIP events on the library's stream at every phase
+boundary) gives the per-phase times: the dominant phase's kernel is the roofline
+entry.  The whole-step algorithmic bytes follow the per-point model of the design
+notes (grid bytes once per cloud and eps, the rest once per setting).  The CPU
+oracle is timed on the host cores on a spatial crop of the first cloud.  With
+--extra (the default) the 1M-point 3D cloud, the 256-cloud batch and the 5D / 7D
+mixtures (float32 filter forced on) are timed too, with fewer steps.
 
 Prints one JSON line.
 """
@@ -26,6 +33,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -34,6 +42,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "exact-DBSCAN points/s on 1 MI355X: batched FP32-filter vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+# vector FP64 = unpacked vector FP32 on MI355X: 256 CUs x 2.4 GHz x 128 flop/clk
+VALU_PEAK_TFLOPS = 78.6
+DEFAULT_WORKLOAD = "sweep3d_n1e7"
 
 
 def workloads():
@@ -82,6 +93,38 @@ def algorithmic_bytes_per_point(phase: str, d: int, f32: bool) -> float:
     return float(table.get(phase, 0.0))
 
 
+# Whole-path model (bytes per point): the grid part (read the input, write the
+# cell-sorted copy, one key + index pass) is paid once per cloud and eps, the rest
+# (three distance phases reading the sorted coordinates, the two outputs) once per
+# setting.  Plain: 16d + 24 and 24d + 5; filter: 12d + 28 and 12d + 5.
+def step_bytes_per_point(d: int, f32: bool) -> tuple[float, float]:
+    if f32:
+        return 12.0 * d + 28.0, 12.0 * d + 5.0
+    return 16.0 * d + 24.0, 24.0 * d + 5.0
+
+
+def step_algorithmic_bytes(items, f32: bool) -> float:
+    total = 0.0
+    for X, st in items:
+        n, d = X.shape
+        grid, per_setting = step_bytes_per_point(d, f32)
+        total += n * (grid * len({e for e, _ in st}) + per_setting * len(st))
+    return total
+
+
+GRID_PHASES = ("bbox", "keys", "radix_sort", "cells", "cell_boxes", "tree")
+
+
+def phase_algorithmic_bytes(phase: str, items, f32: bool) -> float:
+    """Algorithmic bytes of one phase over a whole step (every occurrence)."""
+    total = 0.0
+    for X, st in items:
+        n, d = X.shape
+        reps = len({e for e, _ in st}) if phase in GRID_PHASES else len(st)
+        total += reps * n * algorithmic_bytes_per_point(phase, d, f32)
+    return total
+
+
 # Kernel behind each phase's roofline entry, as rocprofv3 names it.
 PHASE_KERNEL = {
     "cluster_core": "void db::k_bcp<{d}, {f}>(db::Work, int)",
@@ -89,7 +132,7 @@ PHASE_KERNEL = {
     "radix_sort": "db::k_sort_pass(db::Work, int, int)",
     "border": "void db::k_border<{d}, {f}>(db::Work)",
     "cells": "void db::k_cells<{d}>(db::Work, int)",
-    "keys": "void db::k_keys<{d}>(db::Work)",
+    "keys": "void db::k_keys<{d}>(db::Work, int)",
     "cell_boxes": "void db::k_cell_box<{d}>(db::Work, int)",
     "scatter": "db::k_scatter(db::Work)",
 }
@@ -133,8 +176,38 @@ def stored_traffic(workload: str, kernel: str):
                f"WRITE_SIZE x {sc['WRITE_SIZE']}) KiB per dispatch")
 
 
-def cpu_baseline(items, budget_s: float = 25.0):
-    """Time the C oracle on the host cores on (a bounded prefix of) the workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def spatial_crop(X, m: int):
+    """The points of X inside the box [min, min + L]^d with L chosen so that about m
+    points fall inside: a bounded sample with the cloud's own local density (a
+    prefix of a shuffled cloud would thin it out)."""
+    import numpy as np
+
+    lo = X.min(axis=0)
+    span = float((X.max(axis=0) - lo).max())
+    a, b = 0.0, span
+    for _ in range(40):
+        mid = 0.5 * (a + b)
+        if int(np.all(X - lo <= mid, axis=1).sum()) < m:
+            a = mid
+        else:
+            b = mid
+    return np.ascontiguousarray(X[np.all(X - lo <= b, axis=1)])
+
+
+def cpu_baseline(items, budget_s: float = 15.0, budget_1t_s: float = 8.0):
+    """Time the C oracle on the host cores (all of them, then one) on spatial crops of
+    the first cloud at its first setting."""
     from oracle.o1 import build_o1, dbscan_o1, o1_threads
 
     build_o1(force=False)
@@ -142,21 +215,33 @@ def cpu_baseline(items, budget_s: float = 25.0):
     X, st = items[0]
     eps, mp = st[0]
     n = len(X)
-    m = min(n, 50_000)
-    t0 = time.perf_counter()
-    dbscan_o1(X[:m], eps, mp)
-    t_small = time.perf_counter() - t0
-    sample = n if t_small * (n / m) <= budget_s else max(m, min(n, int(m * budget_s / max(t_small, 1e-6))))
-    t0 = time.perf_counter()
-    dbscan_o1(X[:sample], eps, mp)
-    t = time.perf_counter() - t0
+
+    def rate(threads, budget):
+        m = min(n, 20_000)
+        C = spatial_crop(X, m) if m < n else X
+        t0 = time.perf_counter()
+        dbscan_o1(C, eps, mp, threads=threads)
+        t = time.perf_counter() - t0
+        while len(C) < n and t < 0.3 * budget:
+            m = min(n, int(len(C) * min(8.0, max(1.5, 0.8 * budget / max(t, 1e-3)))))
+            C = spatial_crop(X, m) if m < n else X
+            t0 = time.perf_counter()
+            dbscan_o1(C, eps, mp, threads=threads)
+            t = time.perf_counter() - t0
+        return len(C) / t, len(C), t
+
+    v, m, t = rate(cores, budget_s)
+    v1, m1, t1 = rate(1, budget_1t_s)
     return {
-        "value": sample / t,
+        "value": v,
         "unit": "points/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"C oracle (OpenMP, -O3, no FMA) on the first {sample} of {n} points of the "
-                   f"first cloud, eps={eps}, minPts={mp}; {t:.2f} s wall"),
+        "cpu_model": cpu_model(),
+        "sample": (f"C oracle (OpenMP, -O3, no FMA) on a spatial crop of {m} of the {n} points of "
+                   f"the first cloud (a corner box keeping the local density), eps={eps}, "
+                   f"minPts={mp}; {t:.2f} s wall on {cores} threads"),
+        "one_thread": {"value": v1, "unit": "points/s", "sample_points": m1, "seconds": round(t1, 3)},
     }
 
 
@@ -173,20 +258,106 @@ def timed(fn, steps, warmup):
     return time.perf_counter() - t0
 
 
+def prepare(items, dev):
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    clouds = [torch.from_numpy(X).to(dev) for X, _ in items]
+    settings = [st for _, st in items]
+    binding.reserve(max(X.shape[0] for X in clouds), max(X.shape[1] for X in clouds))
+    outs = [[(torch.empty(X.shape[0], dtype=torch.uint8, device=dev),
+              torch.empty(X.shape[0], dtype=torch.int32, device=dev)) for _ in st]
+            for X, st in zip(clouds, settings)]
+    points = sum(X.shape[0] * len(st) for X, st in zip(clouds, settings))
+    return clouds, settings, outs, points
+
+
+def unbatched(clouds, settings, outs, mode):
+    from paper_1912_06255_amd import binding
+
+    def step():
+        for X, st, o in zip(clouds, settings, outs):
+            for (eps, mp), out in zip(st, o):
+                binding.dbscan(X, eps, mp, mode=mode, out=out, check=False)
+    return step
+
+
+def batched_rate(clouds, settings, mode, points, steps, warmup):
+    from paper_1912_06255_amd import binding
+
+    batch = binding.Batch(clouds, settings, mode=mode)
+    batch.run()  # capture + instantiate (reported separately, not timed)
+    t0 = time.perf_counter()
+    batch.run()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    wall = timed(lambda: batch.run(check=False), steps, warmup)
+    st = binding.stats(raise_on_error=True)
+    return batch, points * steps / wall, wall * 1e3 / steps, first_ms, st
+
+
+def extra_workload(name, dev, steps, warmup, filter_max_d=None):
+    """Plain (one call per setting) against the batched float32-filter graph on
+    another workload; per-eps recheck counts and filter band widths for the
+    mixtures (their filter forced on with filter_max_d)."""
+    import torch
+
+    from paper_1912_06255_amd import binding
+
+    gen, desc = workloads()[name]
+    items = gen()
+    clouds, settings, outs, points = prepare(items, dev)
+    if filter_max_d is not None:
+        binding.set_option("filter_max_d", filter_max_d)
+    try:
+        wall = timed(unbatched(clouds, settings, outs, "fp64"), steps, warmup)
+        binding.stats(raise_on_error=True)
+        plain = (points * steps / wall, wall * 1e3 / steps)
+        batch, v, ms, _, st = batched_rate(clouds, settings, "fp32_filter", points, steps, warmup)
+        rec = {"description": desc, "points_per_step": points, "clouds": len(clouds),
+               "settings": sum(len(s) for s in settings), "steps": steps, "warmup": warmup,
+               "plain_fp64": {"value": plain[0], "ms_per_step": plain[1]},
+               "batched_filter": {"value": v, "ms_per_step": ms},
+               "speedup_batched_filter_vs_plain": v / plain[0],
+               "fp64_rechecks_batch": st["fp64_rechecks"]}
+        if filter_max_d is not None:
+            rec["filter_max_d"] = filter_max_d
+            per_eps = []
+            X, st0, o0 = clouds[0], settings[0], outs[0]
+            for (eps, mp), out in zip(st0, o0):
+                binding.dbscan(X, eps, mp, mode="fp32_filter", out=out, check=True)
+                s = binding.stats(raise_on_error=True)
+                e2 = eps * eps
+                per_eps.append({"eps": eps, "min_pts": mp, "fp64_rechecks": s["fp64_rechecks"],
+                                "pair_tests": s["pair_tests"],
+                                "band_width_rel": (s["filter_tout"] - s["filter_tin"]) / e2})
+            rec["filter_per_eps"] = per_eps
+        del batch
+        return rec
+    finally:
+        if filter_max_d is not None:
+            binding.set_option("filter_max_d", -1)
+        del clouds, outs
+        torch.cuda.empty_cache()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="spreader3d_n1e6", choices=sorted(workloads()))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (1M 3D, 256 clouds, 5D/7D mixtures)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the options on the first cloud and setting (both modes) "
                          "before the timed legs; the tuning time is reported, not timed")
     ap.add_argument("--profile-pass", action="store_true",
-                    help="only run the workload a few times in each mode plus a reference "
-                         "elementwise kernel of known size (256 MiB read, 256 MiB written), "
-                         "for rocprofv3 counter runs; prints no JSON")
+                    help="only run the workload a few times (unbatched in both modes, then the "
+                         "batched float32-filter graph) plus a reference elementwise kernel of "
+                         "known size (256 MiB read, 256 MiB written), for rocprofv3 counter "
+                         "runs; prints no JSON")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -202,13 +373,7 @@ def main() -> int:
     gen, desc = workloads()[args.workload]
     items = gen()
     dev = torch.device("cuda:0")
-    clouds = [torch.from_numpy(X).to(dev) for X, _ in items]
-    settings = [st for _, st in items]
-    points = sum(X.shape[0] * len(st) for X, st in zip(clouds, settings))
-    binding.reserve(max(X.shape[0] for X in clouds), max(X.shape[1] for X in clouds))
-    outs = [[(torch.empty(X.shape[0], dtype=torch.uint8, device=dev),
-              torch.empty(X.shape[0], dtype=torch.int32, device=dev)) for _ in st]
-            for X, st in zip(clouds, settings)]
+    clouds, settings, outs, points = prepare(items, dev)
 
     autotune = None
     if args.tune:
@@ -217,63 +382,68 @@ def main() -> int:
         autotune = {m: binding.tune(X0, e0, m0, mode=m) for m in ("fp64", "fp32_filter")}
         autotune["seconds"] = time.perf_counter() - t0
 
-    def unbatched(mode):
-        def step():
-            for X, st, o in zip(clouds, settings, outs):
-                for (eps, mp), out in zip(st, o):
-                    binding.dbscan(X, eps, mp, mode=mode, out=out, check=False)
-        return step
-
     if args.profile_pass:
         for mode in ("fp64", "fp32_filter"):
-            for _ in range(3):
-                unbatched(mode)()
+            for _ in range(2):
+                unbatched(clouds, settings, outs, mode)()
+        b = binding.Batch(clouds, settings, mode="fp32_filter")
+        for _ in range(3):
+            b.run(check=False)
         binding.stats(raise_on_error=True)
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
+        o = torch.empty_like(a)
         for _ in range(3):
-            torch.mul(a, 2.0, out=b)  # reads 256 MiB, writes 256 MiB
+            torch.mul(a, 2.0, out=o)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         print("profile pass done", flush=True)
         return 0
 
     rates = {}
     for leg, mode in (("plain", "fp64"), ("filter", "fp32_filter")):
-        wall = timed(unbatched(mode), args.steps, args.warmup)
+        wall = timed(unbatched(clouds, settings, outs, mode), args.steps, args.warmup)
         binding.stats(raise_on_error=True)
         rates[leg] = (points * args.steps / wall, wall * 1e3 / args.steps)
+        print(f"[bench] {leg}: {rates[leg][1]:.3f} ms/step", file=sys.stderr, flush=True)
 
-    batch = binding.Batch(clouds, settings, mode="fp32_filter")
-    batch.run()  # capture + instantiate (reported separately, not timed)
-    t0 = time.perf_counter()
-    batch.run()
-    first_replay_ms = (time.perf_counter() - t0) * 1e3
-    wall = timed(lambda: batch.run(check=False), args.steps, args.warmup)
-    st = binding.stats(raise_on_error=True)
-    rates["batched"] = (points * args.steps / wall, wall * 1e3 / args.steps)
+    b64, v, ms, _, _ = batched_rate(clouds, settings, "fp64", points, args.steps, args.warmup)
+    rates["batched_fp64"] = (v, ms)
+    del b64
+    batch, v, ms, first_replay_ms, st = batched_rate(clouds, settings, "fp32_filter", points,
+                                                     args.steps, args.warmup)
+    rates["batched"] = (v, ms)
+    print(f"[bench] batched: {ms:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # profiled loop: the filter leg of the first cloud and setting with phase events
-    X0, (eps0, mp0), out0 = clouds[0], settings[0][0], outs[0][0]
-    n0, d0 = X0.shape
+    # profiled steps: the batched float32-filter step run eagerly with phase events
+    prof_steps = max(1, min(args.steps, 5))
     binding.set_profiling(True)
-    acc = {}
+    acc, occ = {}, {}
+    pair_tests = 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
-        binding.dbscan(X0, eps0, mp0, mode="fp32_filter", out=out0, check=False)
-        for k, v in binding.phase_times().items():
-            acc[k] = acc.get(k, 0.0) + v
+    for _ in range(prof_steps):
+        batch.run(check=False)
+        for k, (v_ms, v_occ) in binding.phase_stats().items():
+            acc[k] = acc.get(k, 0.0) + v_ms
+            occ[k] = v_occ
+        pair_tests += binding.stats(raise_on_error=True)["pair_tests"]
     prof_wall = time.perf_counter() - t1
     binding.set_profiling(False)
-    st0 = binding.stats(raise_on_error=True)
-    phase_ms = {k: v / args.steps for k, v in acc.items()}
+    phase_ms = {k: v / prof_steps for k, v in acc.items()}
     dom = max(phase_ms, key=phase_ms.get)
-    launches = {"radix_sort": max(1, (st0["key_bits"] + 7) // 8)}.get(dom, 1)
+    d0 = clouds[0].shape[1]
+    launches = max(1, occ.get(dom, 1))
     per_launch_ms = phase_ms[dom] / launches
-    alg_bytes = algorithmic_bytes_per_point(dom, d0, True) * n0
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    alg_launch = phase_algorithmic_bytes(dom, items, True) / launches
+    achieved = alg_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = PHASE_KERNEL.get(dom, dom).format(d=d0, f="true")
     traffic, traffic_src = stored_traffic(args.workload, kname) or (None, None)
+    step_bytes = step_algorithmic_bytes(items, True)
+    step_gbs = step_bytes / (rates["batched"][1] * 1e-3) / 1e9
+    # float64-equivalent flops of ClusterCore's pair tests: (3d - 1) per pair
+    cc_ms = phase_ms.get("cluster_core", 0.0)
+    cc_launches = max(1, occ.get("cluster_core", 1))
+    flops = (3 * d0 - 1) * pair_tests / prof_steps
+    valu_tflops = flops / (cc_ms * 1e-3) / 1e12 if cc_ms > 0 else 0.0
     roofline = {
         "bound": "hbm",
         "kernel": kname,
@@ -286,7 +456,16 @@ def main() -> int:
         "traffic": None if traffic is None else int(traffic),
         "traffic_source": traffic_src,
         "avg_launch_ms": round(per_launch_ms, 5),
-        "alg_bytes_per_launch": int(alg_bytes),
+        "alg_bytes_per_launch": int(alg_launch),
+        "whole_step": {"alg_bytes": int(step_bytes), "achieved": round(step_gbs, 2), "unit": "GB/s",
+                       "frac": round(step_gbs / HBM_PEAK_GBS, 5),
+                       "model": "per point: 12d+28 B per cloud and eps (grid) + 12d+5 B per setting"},
+        "valu_cluster_core": {"kernel": PHASE_KERNEL["cluster_core"].format(d=d0, f="true"),
+                              "pair_tests_per_step": int(pair_tests / prof_steps),
+                              "flops_per_pair": 3 * d0 - 1,
+                              "avg_launch_ms": round(cc_ms / cc_launches, 5),
+                              "achieved": round(valu_tflops, 4), "peak": VALU_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(valu_tflops / VALU_PEAK_TFLOPS, 7)},
     }
 
     value, ms = rates["batched"]
@@ -307,16 +486,30 @@ def main() -> int:
                    "clouds": len(clouds), "settings": sum(len(s) for s in settings)},
         "plain_fp64": {"value": rates["plain"][0], "ms_per_step": rates["plain"][1]},
         "filter_unbatched": {"value": rates["filter"][0], "ms_per_step": rates["filter"][1]},
+        "batched_fp64": {"value": rates["batched_fp64"][0], "ms_per_step": rates["batched_fp64"][1]},
         "speedup_batched_filter_vs_plain": value / rates["plain"][0],
+        "speedup_batched_fp64_vs_plain": rates["batched_fp64"][0] / rates["plain"][0],
         "graph_first_replay_ms": first_replay_ms,
         "autotune": autotune,
         "roofline": roofline,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
-        "profiled_ms_per_step": prof_wall * 1e3 / args.steps,
-        "stats_batch": {k: st[k] for k in ("bcp_calls", "uf_links", "fp64_rechecks")},
-        "stats_first": {k: st0[k] for k in ("n_cells", "n_unsafe", "n_core", "bcp_calls",
-                                            "uf_links", "fp64_rechecks", "key_bits", "key_shift")},
+        "phase_occurrences": occ,
+        "profiled_ms_per_step": prof_wall * 1e3 / prof_steps,
+        "stats_batch": {k: st[k] for k in ("bcp_calls", "uf_links", "fp64_rechecks", "pair_tests")},
     }
+    del batch, clouds, outs
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        extra = {}
+        for name, fmd in (("spreader3d_n1e6", None), ("multicloud_256", None),
+                          ("mixture5d_n2e6", 8), ("mixture7d_n2e6", 8)):
+            if name == args.workload:
+                continue
+            k = max(1, min(args.steps, 5))
+            extra[name] = extra_workload(name, dev, k, 1, filter_max_d=fmd)
+            print(f"[bench] {name}: batched {extra[name]['batched_filter']['ms_per_step']:.2f} ms/step",
+                  file=sys.stderr, flush=True)
+        out["other_workloads"] = extra
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(items)
     print(json.dumps(out), flush=True)
     return 0

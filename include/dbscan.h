@@ -78,6 +78,8 @@ typedef struct {
   int32_t key_shift;     /* key coordinate = floor(cell index / 2^key_shift) */
   uint32_t status;       /* 0 or a bit set of DBSCAN_STATUS_* */
   uint32_t reserved;
+  float filter_tin;      /* float32 filter thresholds of the last grid built in */
+  float filter_tout;     /* DBSCAN_FP32_FILTER mode: IN if D32 <= tin, OUT if > tout */
 } dbscan_stats;
 
 #define DBSCAN_STATUS_NONFINITE 1u
@@ -175,13 +177,21 @@ int dbscan_get_stats(dbscan_ctx *ctx, void *stream, dbscan_stats *out);
  * Phase timing.  With profiling on, each call records HIP events on its stream
  * between its phases (grid box, keys, radix sort, cell runs, cell boxes and
  * guard, box tree, MarkCore, ClusterCore, relabel, ClusterBorder, output
- * scatter).  dbscan_phase_times() synchronises `stream` and writes up to
- * `cap` per-phase durations in milliseconds of the last call; it returns the
- * number of phases (DBSCAN_NUM_PHASES) or a negative error code.
+ * scatter); a profiled dbscan_batch() runs eagerly (no graph) and records the
+ * same boundaries for every cloud and setting.  dbscan_phase_times()
+ * synchronises `stream` and writes up to `cap` per-phase durations in
+ * milliseconds of the last call, each summed over every occurrence of the phase
+ * in that call (a batch repeats the setting phases once per setting and the grid
+ * phases once per cloud and eps); it returns the number of phases
+ * (DBSCAN_NUM_PHASES) or a negative error code.  dbscan_phase_stats() does the
+ * same and also writes the number of occurrences of each phase to
+ * `occurrences` (may be NULL).
  */
 #define DBSCAN_NUM_PHASES 11
 int dbscan_set_profiling(dbscan_ctx *ctx, int on);
 int dbscan_phase_times(dbscan_ctx *ctx, void *stream, float *ms, int32_t cap);
+int dbscan_phase_stats(dbscan_ctx *ctx, void *stream, float *ms, int32_t *occurrences,
+                       int32_t cap);
 const char *dbscan_phase_name(int32_t phase);
 
 /*

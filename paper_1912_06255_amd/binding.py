@@ -51,6 +51,8 @@ class Stats(ctypes.Structure):
         ("key_shift", ctypes.c_int32),
         ("status", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("filter_tin", ctypes.c_float),
+        ("filter_tout", ctypes.c_float),
     ]
 
     def as_dict(self) -> dict:
@@ -115,6 +117,8 @@ def load():
     lib.dbscan_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.dbscan_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.dbscan_phase_times.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.dbscan_phase_stats.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(i32), i32]
     lib.dbscan_phase_name.argtypes = [i32]
     lib.dbscan_phase_name.restype = ctypes.c_char_p
     lib.dbscan_tune.argtypes = [vp, vp, i64, i32, f64, i32, i32, vp, vp, vp, ctypes.POINTER(Tuned)]
@@ -125,7 +129,7 @@ def load():
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
-              "dbscan_set_profiling", "dbscan_phase_times", "dbscan_set_option", "dbscan_get_option",
+              "dbscan_set_profiling", "dbscan_phase_times", "dbscan_phase_stats", "dbscan_set_option", "dbscan_get_option",
               "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear",
               "dbscan_membership", "dbscan_approx"):
         getattr(lib, f).restype = ctypes.c_int
@@ -293,13 +297,21 @@ def set_profiling(on: bool, device: int = 0) -> None:
 
 
 def phase_times(device: int = 0, stream=None) -> dict:
-    """Per-phase milliseconds of the last call (profiling must be on)."""
+    """Per-phase milliseconds of the last call (profiling must be on), each summed
+    over every occurrence of the phase in that call."""
+    return {k: ms for k, (ms, _) in phase_stats(device, stream).items()}
+
+
+def phase_stats(device: int = 0, stream=None) -> dict:
+    """Per phase of the last call: (milliseconds summed over its occurrences,
+    number of occurrences).  Profiling must be on."""
     lib = load()
     buf = (ctypes.c_float * 32)()
-    k = lib.dbscan_phase_times(context(device), _stream_handle(device, stream), buf, 32)
+    occ = (ctypes.c_int32 * 32)()
+    k = lib.dbscan_phase_stats(context(device), _stream_handle(device, stream), buf, occ, 32)
     if k < 0:
-        raise DbscanError(k, "dbscan_phase_times")
-    return {lib.dbscan_phase_name(i).decode(): float(buf[i]) for i in range(k)}
+        raise DbscanError(k, "dbscan_phase_stats")
+    return {lib.dbscan_phase_name(i).decode(): (float(buf[i]), int(occ[i])) for i in range(k)}
 
 
 def set_option(name: str, value: int, device: int = 0) -> None:

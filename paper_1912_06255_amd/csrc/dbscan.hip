@@ -64,11 +64,13 @@ struct dbscan_ctx {
   // autotuner: choices per (d, mode, size class), used where an option is automatic
   std::vector<TunedEntry> tuned;
   uint32_t tune_gen = 0;
-  // profiling
+  // profiling: one event per phase boundary of the last call, in order, with the
+  // boundary's index (a pool reused from call to call)
   bool profile = false;
-  bool events_ready = false;
   bool events_recorded = false;
-  hipEvent_t ev[DBSCAN_NUM_PHASES + 1];
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_mark;
+  bool ev_error = false;
   // captured batch
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -185,13 +187,34 @@ const char* const kPhaseNames[DBSCAN_NUM_PHASES] = {
     "bbox", "keys", "radix_sort", "cells", "cell_boxes", "tree", "markcore",
     "cluster_core", "relabel", "border", "scatter"};
 
+// Phase boundaries: mark(i) ends phase i - 1 (and starts phase i).  With profiling
+// on, each boundary records an event; the time between two consecutive events is
+// charged to the phase the later one ends, so a batch, which repeats phases (the
+// setting stages once per setting), sums every occurrence.
 struct Marks {
-  hipEvent_t* ev;  // null when profiling is off
+  dbscan_ctx* ctx;  // null when profiling is off
   hipStream_t s;
   void operator()(int i) const {
-    if (ev) (void)hipEventRecord(ev[i], s);
+    if (!ctx) return;
+    const size_t k = ctx->ev_mark.size();
+    if (k == ctx->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        ctx->ev_error = true;
+        return;
+      }
+      ctx->ev_pool.push_back(e);
+    }
+    if (hipEventRecord(ctx->ev_pool[k], s) != hipSuccess) ctx->ev_error = true;
+    ctx->ev_mark.push_back(i);
   }
 };
+
+void reset_marks(dbscan_ctx* ctx) {
+  ctx->ev_mark.clear();
+  ctx->ev_error = false;
+  ctx->events_recorded = ctx->profile;
+}
 
 // ---------------------------------------------------------------------------
 // Launch stages.  grid: cells, boxes, guard, tree (and the float32 coordinates
@@ -370,8 +393,7 @@ int check_args(int64_t n, int32_t d, double eps, int32_t min_pts) {
 // instance with equal eps share the grid and one neighbour count, taken up to the
 // largest of their minPts.
 int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, bool f32,
-                  hipStream_t s) {
-  const Marks none{nullptr, s};
+                  hipStream_t s, const Marks& none) {
   bool first = true;
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -520,8 +542,7 @@ int dbscan_ctx_destroy(dbscan_ctx* ctx) {
   drop_graph(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->scratch && hipFree(ctx->scratch) != hipSuccess) rc = DBSCAN_EHIP;
-  if (ctx->events_ready)
-    for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i) (void)hipEventDestroy(ctx->ev[i]);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return rc;
 }
@@ -557,13 +578,8 @@ int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double 
   ctx->last_work = W;
   ctx->stats_valid = true;
   ctx->stats_work = W;
-  if (ctx->profile && !ctx->events_ready) {
-    for (int i = 0; i <= DBSCAN_NUM_PHASES; ++i)
-      if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return DBSCAN_EHIP;
-    ctx->events_ready = true;
-  }
-  const Marks mark{ctx->profile ? ctx->ev : nullptr, s};
-  ctx->events_recorded = ctx->profile;
+  reset_marks(ctx);
+  const Marks mark{ctx->profile ? ctx : nullptr, s};
   const Stages st = stages_for(d, use_filter(ctx, mode, d));
   st.grid(W, s, mark, eps, true);
   st.count(W, s);
@@ -849,12 +865,14 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
   int rc = grow(ctx, nmax, dmax);
   if (rc != DBSCAN_OK) return rc;
-  ctx->events_recorded = false;
   ctx->last_n = 0;
   for (int32_t i = 0; i < count; ++i) ctx->last_n += inst[i].n * inst[i].n_settings;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool f32 = mode == DBSCAN_FP32_FILTER;
-  if (!ctx->batch_graph) return enqueue_batch(ctx, inst, count, f32, s);
+  reset_marks(ctx);
+  // profiled batches run eagerly, with an event at every phase boundary
+  if (ctx->profile) return enqueue_batch(ctx, inst, count, f32, s, Marks{ctx, s});
+  if (!ctx->batch_graph) return enqueue_batch(ctx, inst, count, f32, s, Marks{nullptr, s});
 
   std::vector<unsigned char> key = batch_key(ctx, inst, count, mode);
   if (!ctx->graph || key != ctx->graph_key) {
@@ -864,7 +882,7 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
       return DBSCAN_EHIP;
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return DBSCAN_EHIP;
-    rc = enqueue_batch(ctx, inst, count, f32, ctx->cap_stream);
+    rc = enqueue_batch(ctx, inst, count, f32, ctx->cap_stream, Marks{nullptr, ctx->cap_stream});
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (rc != DBSCAN_OK || e != hipSuccess || !g) {
@@ -905,6 +923,8 @@ int dbscan_get_stats(dbscan_ctx* ctx, void* stream, dbscan_stats* out) {
   out->key_bits = g.total_bits;
   out->key_shift = g.shift;
   out->status = g.status;
+  out->filter_tin = g.tin;
+  out->filter_tout = g.tout;
   if (g.status & DBSCAN_STATUS_NONFINITE) return DBSCAN_ENONFINITE;
   if (g.status & DBSCAN_STATUS_WAIT_EXPIRED) return DBSCAN_EINTERNAL;
   return DBSCAN_OK;
@@ -971,12 +991,30 @@ int dbscan_set_profiling(dbscan_ctx* ctx, int on) {
 }
 
 int dbscan_phase_times(dbscan_ctx* ctx, void* stream, float* ms, int32_t cap) {
+  return dbscan_phase_stats(ctx, stream, ms, nullptr, cap);
+}
+
+int dbscan_phase_stats(dbscan_ctx* ctx, void* stream, float* ms, int32_t* occurrences,
+                       int32_t cap) {
   if (!ctx || !ms || cap < 0) return DBSCAN_EINVAL;
   if (!ctx->events_recorded) return DBSCAN_EINVAL;
+  if (ctx->ev_error) return DBSCAN_EHIP;
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DBSCAN_EHIP;
+  float sum[DBSCAN_NUM_PHASES] = {};
+  int32_t occ[DBSCAN_NUM_PHASES] = {};
+  for (size_t k = 1; k < ctx->ev_mark.size(); ++k) {
+    const int ph = ctx->ev_mark[k] - 1;  // the phase this boundary ends
+    if (ph < 0 || ph >= DBSCAN_NUM_PHASES) continue;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, ctx->ev_pool[k - 1], ctx->ev_pool[k]) != hipSuccess)
+      return DBSCAN_EHIP;
+    sum[ph] += t;
+    ++occ[ph];
+  }
   for (int i = 0; i < DBSCAN_NUM_PHASES && i < cap; ++i) {
-    if (hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]) != hipSuccess) return DBSCAN_EHIP;
+    ms[i] = sum[i];
+    if (occurrences) occurrences[i] = occ[i];
   }
   return DBSCAN_NUM_PHASES;
 }

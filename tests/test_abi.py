@@ -54,5 +54,7 @@ def test_null_arguments_are_rejected_without_touching_a_gpu(lib):
 
 
 def test_stats_struct_matches_header():
-    # int64 x8 + int32 x2 + uint32 x2
-    assert ctypes.sizeof(binding.Stats) == 8 * 8 + 4 * 4
+    # int64 x8 + int32 x2 + uint32 x2 + float x2
+    assert ctypes.sizeof(binding.Stats) == 8 * 8 + 4 * 4 + 4 * 2
+    names = [f for f, _ in binding.Stats._fields_]
+    assert names[-2:] == ["filter_tin", "filter_tout"]

@@ -45,3 +45,29 @@ def test_gpus_other_than_one_exit(monkeypatch, capsys):
     assert bench.main() == 2
     assert "one GPU" in capsys.readouterr().err
     assert os.environ.get("WORLD_SIZE", "1") == "1"
+
+
+def test_step_bytes_model():
+    import numpy as np
+
+    # float32 filter: 12d + 28 per cloud and eps, 12d + 5 per setting; float64: 16d + 24, 24d + 5
+    X = np.zeros((1000, 3))
+    items = [(X, [(1.0, 5), (1.0, 10), (2.0, 5)])]
+    assert bench.step_algorithmic_bytes(items, True) == 1000 * (2 * (12 * 3 + 28) + 3 * (12 * 3 + 5))
+    assert bench.step_algorithmic_bytes(items, False) == 1000 * (2 * (16 * 3 + 24) + 3 * (24 * 3 + 5))
+    # grid phases once per eps, the others once per setting
+    assert bench.phase_algorithmic_bytes("keys", items, True) == 2 * 1000 * (8 * 3 + 12)
+    assert bench.phase_algorithmic_bytes("cluster_core", items, True) == 3 * 1000 * (4 * 3 + 1)
+
+
+def test_spatial_crop_keeps_density():
+    import numpy as np
+
+    rng = np.random.default_rng(5)
+    X = rng.uniform(0.0, 100.0, size=(200_000, 3))
+    C = bench.spatial_crop(X, 5_000)
+    assert 4_900 <= len(C) <= 5_100
+    side = float((C.max(axis=0) - X.min(axis=0)).max())
+    # uniform density 200k / 1e6: the crop's box holds the same density
+    assert abs(len(C) / side ** 3 - 0.2) < 0.03
+    assert np.all(C <= X.min(axis=0) + side + 1e-9)
