@@ -104,6 +104,11 @@ def load():
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1912_06255_amd.build`"
         )
+    # PyTorch first: its HIP runtime is then the one the library binds to.  Loaded
+    # the other way round, the library would pull in a second HIP runtime whose
+    # device state and streams are not PyTorch's.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.dbscan_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]

@@ -257,7 +257,7 @@ DB_DEV void walk_from_list(const Work& W, int C, int g, const Query<D>& q, V& vi
   if (lane < len) {
     node = W.nlist[(size_t)G * kNodeList + lane];
     const double bd = box_sqdist<D>(q.lo, q.hi, W.tree.flo[1], W.tree.fhi[1], W.tree.cap[1], node);
-    if (bd <= q.E2) dist = bd;
+    if (bd <= q.E2 && vis.keep_node(1, node)) dist = bd;
   }
   uint64_t todo = ballot(dist <= q.E2);
   while (todo) {
@@ -741,6 +741,95 @@ __global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
   }
 }
 
+// The settings of one eps (up to kMultiMax, by decreasing minPts) from the one
+// neighbour count: bit s of coreS is the core flag under minPts[s], and each
+// setting gets its own per-cell core count, smallest core input index and root
+// minimum.  The union-find starts at the identity unless `warm` (a further group
+// of the same eps continues from the previous group's links).
+constexpr int kMultiMax = 8;
+struct MultiCore {
+  int k, warm;
+  int minPts[kMultiMax];
+  int32_t* coreCount[kMultiMax];
+  int32_t* cellMin[kMultiMax];
+  int32_t* minIdx[kMultiMax];
+};
+
+__global__ __launch_bounds__(kBlock) void k_core_multi(Work W, MultiCore M) {
+  const int C = W.desc->n_cells;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+    const int s = W.cellStart[g], e = W.cellStart[g + 1];
+    int cc[kMultiMax], mn[kMultiMax];
+#pragma unroll
+    for (int t = 0; t < kMultiMax; ++t) {
+      cc[t] = 0;
+      mn[t] = kIntMax;
+    }
+    for (int i0 = s; i0 < e; i0 += 4 * kWave) {
+      int c[4], pm[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kWave + lane;
+        c[u] = i < e ? W.cnt[i] : -1;
+        pm[u] = i < e ? W.perm[i] : kIntMax;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kWave + lane;
+        uint32_t bits = 0;
+#pragma unroll
+        for (int t = 0; t < kMultiMax; ++t) {
+          const bool core = t < M.k && c[u] >= M.minPts[t];
+          bits |= core ? (1u << t) : 0u;
+          cc[t] += core ? 1 : 0;
+          mn[t] = core ? min(mn[t], pm[u]) : mn[t];
+        }
+        if (i < e) W.coreS[i] = (uint8_t)bits;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kMultiMax; ++t) {
+      if (t >= M.k) break;
+      const int a = wave_sum(cc[t]), b = wave_min(mn[t]);
+      if (lane == 0) {
+        M.coreCount[t][g] = a;
+        M.cellMin[t][g] = b;
+        M.minIdx[t][g] = kIntMax;
+      }
+    }
+    if (lane == 0 && !M.warm) W.parent[g] = g;
+  }
+}
+
+// Outputs of the settings of one eps in input order: position j of every output
+// array is written by one thread (coalesced stores), which reads its sorted
+// position through the inverse permutation and the setting's cell label (core
+// points) or border label.
+struct MultiOut {
+  int k;
+  uint8_t* core[kMultiMax];
+  int32_t* label[kMultiMax];
+  const int32_t* cellLabel[kMultiMax];
+  const int32_t* blabel[kMultiMax];
+};
+
+__global__ void k_output_multi(Work W, MultiOut O) {
+  const int n = W.n;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int i = W.inv[j];
+    const int c = W.cellOf[i];
+    const uint32_t bits = W.coreS[i];
+#pragma unroll
+    for (int t = 0; t < kMultiMax; ++t) {
+      if (t >= O.k) break;
+      const bool core = (bits >> t) & 1u;
+      O.core[t][j] = core ? 1 : 0;
+      O.label[t][j] = core ? O.cellLabel[t][c] : O.blabel[t][i];
+    }
+  }
+}
+
 // Number of core points of the last setting, for the statistics (not on the hot
 // path: run when they are read).  One workgroup sums the per-cell core counts.
 __global__ __launch_bounds__(kBlock) void k_core_total(Work W) {
@@ -807,7 +896,7 @@ struct BcpVisitor {
         load_local<D>(W->X32, W->n, i, a);
         cell = W->cellOf[i];
       }
-      v = core != 0;
+      v = (core & W->core_mask) != 0;
     }
   }
 
@@ -891,7 +980,7 @@ struct BcpVisitor {
       const uint8_t core = W->coreS[q];
       load_point<D>(W->X, W->n, q, xq);
       if constexpr (F32) load_local<D>(W->X32, W->n, q, aq);
-      valid = core != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
+      valid = (core & W->core_mask) != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
     }
     return valid;
   }
@@ -1061,7 +1150,7 @@ struct BcpVisitor {
         load_point<D>(W->X, n, q, xq);
         if constexpr (F32) load_local<D>(W->X32, n, q, aq);
         // points of h farther than eps from the unit's box drop out
-        valid = core != 0 && ((alive >> j) & 1ull) &&
+        valid = (core & W->core_mask) != 0 && ((alive >> j) & 1ull) &&
                 box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
       }
       if (!ballot(valid)) continue;
@@ -1228,10 +1317,11 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     }
     v.c0 = v.ps >> 6;
     v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
-    v.rg = v.ucell;
+    // a warm start prunes by the node roots taken before the launch from the start
+    v.rg = W.warm ? uf_find(W.parent, v.ucell) : v.ucell;
     v.excl_level = round >= 1 ? round : -1;
     v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
-    v.prune = round >= 1;
+    v.prune = round >= 1 || W.warm != 0;
     const int anc_level = round < 0 ? top + 1 : round + 1;
     const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
     if (round < 0 && ulevel == 0)
@@ -1353,7 +1443,7 @@ struct BorderVisitor {
       }
       if (valid) {
         locate(F, k, j, q);
-        valid = W->coreS[q] != 0;
+        valid = (W->coreS[q] & W->core_mask) != 0;
       }
       if (valid) {
         lq = W->cellLabel[cb + j];
@@ -1415,7 +1505,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Work W) {
       int taken = 0;
       while (i < e && taken < kWave) {
         const int k = i + lane;
-        const bool nc = k < e && W.coreS[k] == 0;
+        const bool nc = k < e && (W.coreS[k] & W.core_mask) == 0;
         const uint64_t bm = ballot(nc);
         const int rank = __popcll(bm & lanemask_lt());
         const int cnt = __popcll(bm);
@@ -1466,7 +1556,7 @@ __global__ void k_scatter(Work W) {
   const int n = W.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int src = W.perm[i];
-    const uint8_t c = W.coreS[i];
+    const uint8_t c = (W.coreS[i] & W.core_mask) ? 1 : 0;
     W.core_out[src] = c;
     W.label_out[src] = c ? W.cellLabel[W.cellOf[i]] : W.blabel[i];
   }

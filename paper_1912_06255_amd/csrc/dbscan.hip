@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -98,7 +99,10 @@ struct Carver {
   }
 };
 
-size_t layout(char* base, int64_t n, int d, Work* W) {
+// slots: settings whose per-setting arrays coexist (several settings of one eps,
+// computed together); 1 for a single setting.
+// keep_keys: a copy of the sorted keys for grids derived from a finer one.
+size_t layout(char* base, int64_t n, int d, Work* W, int slots = 1, bool keep_keys = false) {
   Work tmp;
   Work& w = W ? *W : tmp;
   Carver c{base};
@@ -138,12 +142,15 @@ size_t layout(char* base, int64_t n, int d, Work* W) {
   w.nlen = c.take<int32_t>(w.tree.cap[1]);
   w.coreS = c.take<uint8_t>(n);
   w.cnt = c.take<int32_t>(n);
-  w.coreCount = c.take<int32_t>(n);
   w.parent = c.take<int32_t>(n);
-  w.minIdx = c.take<int32_t>(n);
-  w.cellLabel = c.take<int32_t>(n);
-  w.cellMin = c.take<int32_t>(n);
-  w.blabel = c.take<int32_t>(n);
+  const int64_t ns = n * (int64_t)std::max(1, slots);
+  w.coreCount = c.take<int32_t>(ns);
+  w.minIdx = c.take<int32_t>(ns);
+  w.cellLabel = c.take<int32_t>(ns);
+  w.cellMin = c.take<int32_t>(ns);
+  w.blabel = c.take<int32_t>(ns);
+  w.inv = slots > 1 ? c.take<int32_t>(n) : nullptr;
+  w.skey = keep_keys ? c.take<uint64_t>(n) : nullptr;
   return c.off;
 }
 
@@ -153,8 +160,8 @@ void drop_graph(dbscan_ctx* ctx) {
   ctx->graph_key.clear();
 }
 
-int grow(dbscan_ctx* ctx, int64_t n, int d) {
-  const size_t need = ctx->desc_bytes + layout(nullptr, n, d, nullptr);
+int grow(dbscan_ctx* ctx, int64_t n, int d, int slots = 1, bool keep_keys = false) {
+  const size_t need = ctx->desc_bytes + layout(nullptr, n, d, nullptr, slots, keep_keys);
   if (need <= ctx->scratch_bytes) return DBSCAN_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
   if (hipDeviceSynchronize() != hipSuccess) return DBSCAN_EHIP;
@@ -221,11 +228,28 @@ void reset_marks(dbscan_ctx* ctx) {
 // and thresholds); count: MarkCore neighbour counts up to count_cap; setting:
 // core flags of one minPts, ClusterCore, relabel, ClusterBorder, scatter.
 // ---------------------------------------------------------------------------
+// The grid after the cell runs: boxes, guard and split, sub-cell order, box tree,
+// node lists and float32 coordinates.
+template <int D, bool F32>
+void stage_grid_back(const Work& W, hipStream_t s, const Marks& mark, double eps);
+
+// A grid cut from the previous (finer) grid of the same cloud: eps = 2^j times its eps.
+template <int D, bool F32>
+void stage_grid_derived(const Work& W, hipStream_t s, const Marks& mark, double eps, int j) {
+  const unsigned tiles = (unsigned)ceil_div(W.n, kTile);
+  mark(0);
+  k_derive<D><<<1, kBlock, 0, s>>>(W, j);
+  mark(1);
+  mark(2);
+  mark(3);
+  k_cells<D><<<tiles, kBlock, 0, s>>>(W, 2);
+  mark(4);
+  stage_grid_back<D, F32>(W, s, mark, eps);
+}
+
 template <int D, bool F32>
 void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, bool first) {
   const int64_t n = W.n;
-  const unsigned gp = grid_for(n, kBlock, 2048);
-  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
   const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
   const unsigned tiles = (unsigned)ceil_div(n, kTile);
   mark(0);
@@ -239,6 +263,15 @@ void stage_grid(const Work& W, hipStream_t s, const Marks& mark, double eps, boo
   mark(3);
   k_cells<D><<<tiles, kBlock, 0, s>>>(W, 0);
   mark(4);
+  stage_grid_back<D, F32>(W, s, mark, eps);
+}
+
+template <int D, bool F32>
+void stage_grid_back(const Work& W, hipStream_t s, const Marks& mark, double eps) {
+  const int64_t n = W.n;
+  const unsigned gp = grid_for(n, kBlock, 2048);
+  const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
+  const unsigned tiles = (unsigned)ceil_div(n, kTile);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(W, 0);
   k_cell_safe<D><<<gp, kBlock, 0, s>>>(W);
   // cells that fail the float64 diameter guard become singletons
@@ -268,23 +301,26 @@ void stage_count(const Work& W, hipStream_t s) {
                         kBlock, 0, s>>>(W);
 }
 
+// ClusterCore, cluster ids and ClusterBorder of one setting whose core flags are
+// set.  A warm start (W.warm) first takes the node roots of the union-find the
+// previous setting left, so that ClusterCore prunes subtrees already joined.
 template <int D, bool F32>
-void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
+void stage_cluster(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
   const int64_t n = W.n;
   const unsigned gp = grid_for(n, kBlock, 2048);
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
   const unsigned gb = grid_for(n * W.bcp_split, kWavesPerBlock, 8192);
   const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
-  k_core_from_count<<<gw, kBlock, 0, s>>>(W);
-  mark(7);
+  auto node_roots = [&]() {
+    for (int l = 1; l <= kTreeLevels; ++l)
+      k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
+  };
   if (!rounds) {
+    if (W.warm) node_roots();
     k_bcp<D, F32><<<gb, kBlock, 0, s>>>(W, -1);
   } else {
     for (int round = 0; round < kTreeLevels; ++round) {
-      if (round > 0) {
-        for (int l = 1; l <= kTreeLevels; ++l)
-          k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(W, l);
-      }
+      if (round > 0 || W.warm) node_roots();
       k_bcp<D, F32><<<gb, kBlock, 0, s>>>(W, round);
     }
   }
@@ -294,19 +330,32 @@ void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds)
   mark(9);
   k_border<D, F32><<<gw, kBlock, 0, s>>>(W);
   mark(10);
+}
+
+template <int D, bool F32>
+void stage_setting(const Work& W, hipStream_t s, const Marks& mark, bool rounds) {
+  const int64_t n = W.n;
+  const unsigned gp = grid_for(n, kBlock, 2048);
+  const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
+  k_core_from_count<<<gw, kBlock, 0, s>>>(W);
+  mark(7);
+  stage_cluster<D, F32>(W, s, mark, rounds);
   k_scatter<<<gp, kBlock, 0, s>>>(W);
   mark(11);
 }
 
 struct Stages {
   void (*grid)(const Work&, hipStream_t, const Marks&, double, bool);
+  void (*derived)(const Work&, hipStream_t, const Marks&, double, int);
   void (*count)(const Work&, hipStream_t);
   void (*setting)(const Work&, hipStream_t, const Marks&, bool);
+  void (*cluster)(const Work&, hipStream_t, const Marks&, bool);
 };
 
 template <int D, bool F32>
 Stages stages_of() {
-  return Stages{&stage_grid<D, F32>, &stage_count<D, F32>, &stage_setting<D, F32>};
+  return Stages{&stage_grid<D, F32>, &stage_grid_derived<D, F32>, &stage_count<D, F32>,
+                &stage_setting<D, F32>, &stage_cluster<D, F32>};
 }
 
 Stages stages_for(int d, bool f32) {
@@ -324,7 +373,7 @@ Stages stages_for(int d, bool f32) {
     DB_STAGES(8)
 #undef DB_STAGES
   }
-  return Stages{nullptr, nullptr, nullptr};
+  return Stages{nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 // Whether a call in `mode` takes its pair decisions through the float32 filter:
@@ -365,7 +414,7 @@ Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
 
 // Fields of Work shared by every stage of one grid.
 void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d, double eps,
-               const Resolved& R) {
+               const Resolved& R, int slots = 1, bool keep_keys = false) {
   std::memset(static_cast<void*>(&W), 0, sizeof(W));
   W.n = (int)n;
   W.E2 = eps * eps;
@@ -380,7 +429,9 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
   W.bcp_split = R.split;
-  layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W);
+  W.warm = 0;
+  W.core_mask = 1u;
+  layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W, slots, keep_keys);
 }
 
 int check_args(int64_t n, int32_t d, double eps, int32_t min_pts) {
@@ -389,11 +440,73 @@ int check_args(int64_t n, int32_t d, double eps, int32_t min_pts) {
   return DBSCAN_OK;
 }
 
+// Most settings of one eps in a batch (kMultiMax per group of per-setting arrays).
+int batch_slots(const dbscan_instance* inst, int32_t count) {
+  int slots = 1;
+  for (int32_t i = 0; i < count; ++i) {
+    const dbscan_instance& I = inst[i];
+    for (int32_t a = 0; a < I.n_settings; ++a) {
+      int same = 0;
+      for (int32_t b = 0; b < I.n_settings; ++b) same += I.eps[b] == I.eps[a];
+      slots = std::max(slots, std::min(same, kMultiMax));
+    }
+  }
+  return slots;
+}
+
+// The grids of one cloud, one per distinct eps.  Eps values that differ by a power
+// of two (equal binary mantissas) form a chain, taken in increasing order: the
+// first grid of a chain is sorted and keeps its sorted keys, each further one is
+// cut from the one before (derive_j levels coarser) without sorting again.
+struct EpsStep {
+  double eps;
+  int derive_j;    // 0: a sorted grid; j > 0: cut from the previous grid (eps / 2^j)
+  bool keep_keys;  // a later grid of the chain is cut from this one
+};
+
+std::vector<EpsStep> eps_plan(const dbscan_instance& I) {
+  std::vector<double> es;
+  for (int32_t a = 0; a < I.n_settings; ++a)
+    if (std::find(es.begin(), es.end(), I.eps[a]) == es.end()) es.push_back(I.eps[a]);
+  std::vector<EpsStep> plan;
+  std::vector<char> used(es.size(), 0);
+  for (size_t a = 0; a < es.size(); ++a) {
+    if (used[a]) continue;
+    int ea;
+    const double ma = std::frexp(es[a], &ea);
+    std::vector<std::pair<int, double>> chain;  // (exponent, eps)
+    for (size_t b = a; b < es.size(); ++b) {
+      int eb;
+      if (!used[b] && std::frexp(es[b], &eb) == ma) {
+        used[b] = 1;
+        chain.push_back({eb, es[b]});
+      }
+    }
+    std::sort(chain.begin(), chain.end());
+    for (size_t c = 0; c < chain.size(); ++c)
+      plan.push_back(EpsStep{chain[c].second, c == 0 ? 0 : chain[c].first - chain[c - 1].first,
+                             c + 1 < chain.size()});
+  }
+  return plan;
+}
+
+bool plan_keeps_keys(const dbscan_instance* inst, int32_t count) {
+  for (int32_t i = 0; i < count; ++i)
+    for (const EpsStep& P : eps_plan(inst[i]))
+      if (P.keep_keys) return true;
+  return false;
+}
+
 // Enqueue a whole batch on stream s (eagerly or under capture).  Settings of one
 // instance with equal eps share the grid and one neighbour count, taken up to the
-// largest of their minPts.
+// largest of their minPts.  They are taken by decreasing minPts: the core points of
+// a smaller minPts include those of a larger one, so every link the larger one made
+// is a link of the smaller one too, and ClusterCore starts from the union-find the
+// previous setting left (it then only tests cells not yet joined).  Their core
+// flags are set together (one bit per setting) and their outputs are written
+// together, in input order, after the last of them.
 int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, bool f32,
-                  hipStream_t s, const Marks& none) {
+                  hipStream_t s, const Marks& marks, int slots, bool keep_keys) {
   bool first = true;
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -402,29 +515,75 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
     const Stages st = stages_for(I.d, use_filter(ctx, mode, I.d));
     const Resolved R = resolve(ctx, I.n, I.d, mode);
     const bool rounds = R.rounds != 0;
-    std::vector<char> done((size_t)I.n_settings, 0);
-    for (int32_t a = 0; a < I.n_settings; ++a) {
-      if (done[a]) continue;
-      const double eps = I.eps[a];
-      int cap = 0;
-      for (int32_t b = a; b < I.n_settings; ++b)
-        if (I.eps[b] == eps) cap = std::max(cap, (int)I.min_pts[b]);
+    const int64_t n = I.n;
+    const std::vector<EpsStep> plan = eps_plan(I);
+    for (size_t pi = 0; pi < plan.size(); ++pi) {
+      const EpsStep& P = plan[pi];
+      const double eps = P.eps;
+      std::vector<int> grp;
+      for (int32_t b = 0; b < I.n_settings; ++b)
+        if (I.eps[b] == eps) grp.push_back(b);
+      std::stable_sort(grp.begin(), grp.end(),
+                       [&](int x, int y) { return I.min_pts[x] > I.min_pts[y]; });
       Work W;
-      fill_work(ctx, W, I.points, I.n, I.d, eps, R);
-      W.count_cap = cap;
-      st.grid(W, s, none, eps, first);
+      fill_work(ctx, W, I.points, n, I.d, eps, R, slots, keep_keys);
+      W.count_cap = I.min_pts[grp[0]];
+      // (the inverse permutation, when kept, follows every grid of the batch: a later
+      // grid of the same chain keeps this one's order)
+      if (!P.keep_keys && P.derive_j == 0) W.skey = nullptr;  // a cut grid reads the kept keys
+      if (P.derive_j > 0) st.derived(W, s, marks, eps, P.derive_j);
+      else st.grid(W, s, marks, eps, first);
       first = false;
       st.count(W, s);
-      for (int32_t b = a; b < I.n_settings; ++b) {
-        if (I.eps[b] != eps) continue;
-        done[b] = 1;
+      if (grp.size() == 1) {
         Work Ws = W;
-        Ws.minPts = I.min_pts[b];
-        Ws.core_out = I.core_flags + (size_t)b * (size_t)I.n;
-        Ws.label_out = I.cluster_id + (size_t)b * (size_t)I.n;
-        st.setting(Ws, s, none, rounds);
+        Ws.minPts = I.min_pts[grp[0]];
+        Ws.core_out = I.core_flags + (size_t)grp[0] * (size_t)n;
+        Ws.label_out = I.cluster_id + (size_t)grp[0] * (size_t)n;
+        st.setting(Ws, s, marks, rounds);
         ctx->stats_valid = true;
         ctx->stats_work = Ws;
+        continue;
+      }
+      const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
+      const unsigned gp = grid_for(n, kBlock, 2048);
+      for (size_t c0 = 0; c0 < grp.size(); c0 += kMultiMax) {
+        const int k = (int)std::min<size_t>(kMultiMax, grp.size() - c0);
+        MultiCore M{};
+        MultiOut O{};
+        M.k = O.k = k;
+        M.warm = c0 > 0;
+        for (int t = 0; t < k; ++t) {
+          M.minPts[t] = I.min_pts[grp[c0 + t]];
+          M.coreCount[t] = W.coreCount + (size_t)t * n;
+          M.cellMin[t] = W.cellMin + (size_t)t * n;
+          M.minIdx[t] = W.minIdx + (size_t)t * n;
+        }
+        k_core_multi<<<gw, kBlock, 0, s>>>(W, M);
+        marks(7);
+        for (int t = 0; t < k; ++t) {
+          const int b = grp[c0 + t];
+          Work Ws = W;
+          Ws.minPts = I.min_pts[b];
+          Ws.core_mask = 1u << t;
+          Ws.warm = (c0 + t) > 0;
+          Ws.coreCount = M.coreCount[t];
+          Ws.cellMin = M.cellMin[t];
+          Ws.minIdx = M.minIdx[t];
+          Ws.cellLabel = W.cellLabel + (size_t)t * n;
+          Ws.blabel = W.blabel + (size_t)t * n;
+          Ws.core_out = I.core_flags + (size_t)b * (size_t)n;
+          Ws.label_out = I.cluster_id + (size_t)b * (size_t)n;
+          st.cluster(Ws, s, marks, rounds);
+          O.core[t] = Ws.core_out;
+          O.label[t] = Ws.label_out;
+          O.cellLabel[t] = Ws.cellLabel;
+          O.blabel[t] = Ws.blabel;
+          ctx->stats_valid = true;
+          ctx->stats_work = Ws;
+        }
+        k_output_multi<<<gp, kBlock, 0, s>>>(W, O);
+        marks(11);
       }
     }
   }
@@ -863,7 +1022,9 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
     dmax = std::max(dmax, I.d);
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
-  int rc = grow(ctx, nmax, dmax);
+  const int slots = batch_slots(inst, count);
+  const bool keep_keys = plan_keeps_keys(inst, count);
+  int rc = grow(ctx, nmax, dmax, slots, keep_keys);
   if (rc != DBSCAN_OK) return rc;
   ctx->last_n = 0;
   for (int32_t i = 0; i < count; ++i) ctx->last_n += inst[i].n * inst[i].n_settings;
@@ -871,8 +1032,10 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
   const bool f32 = mode == DBSCAN_FP32_FILTER;
   reset_marks(ctx);
   // profiled batches run eagerly, with an event at every phase boundary
-  if (ctx->profile) return enqueue_batch(ctx, inst, count, f32, s, Marks{ctx, s});
-  if (!ctx->batch_graph) return enqueue_batch(ctx, inst, count, f32, s, Marks{nullptr, s});
+  if (ctx->profile)
+    return enqueue_batch(ctx, inst, count, f32, s, Marks{ctx, s}, slots, keep_keys);
+  if (!ctx->batch_graph)
+    return enqueue_batch(ctx, inst, count, f32, s, Marks{nullptr, s}, slots, keep_keys);
 
   std::vector<unsigned char> key = batch_key(ctx, inst, count, mode);
   if (!ctx->graph || key != ctx->graph_key) {
@@ -882,7 +1045,8 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
       return DBSCAN_EHIP;
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return DBSCAN_EHIP;
-    rc = enqueue_batch(ctx, inst, count, f32, ctx->cap_stream, Marks{nullptr, ctx->cap_stream});
+    rc = enqueue_batch(ctx, inst, count, f32, ctx->cap_stream, Marks{nullptr, ctx->cap_stream},
+                       slots, keep_keys);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (rc != DBSCAN_OK || e != hipSuccess || !g) {

@@ -75,6 +75,9 @@ struct Work {
   int count_cap;      // MarkCore counts neighbours up to this value (largest minPts of the eps)
   int bcp_split;      // waves per ClusterCore unit
   int sub_min;        // cells of at least this many points get sub-cell order (k_subsort); kIntMax: none
+  int warm;           // ClusterCore starts from the union-find the previous setting left (a larger
+                      // minPts of the same eps: its core points, hence its links, are a subset)
+  uint32_t core_mask; // bit of this setting in coreS (settings of one eps share one byte per point)
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double E2;
   double E2b;         // ClusterCore's pair test: E2, or fl(R^2), R = fl(eps fl(1 + rho)), for approximate DBSCAN
@@ -99,6 +102,9 @@ struct Work {
   double* chunkHi;
   int chunkCap;
   int32_t* perm;      // sorted position -> input index
+  int32_t* inv;       // input index -> sorted position (kept only when several settings share a grid)
+  uint64_t* skey;     // [n] sorted keys of the finest grid of a chain of eps values that differ by
+                      // powers of two (coarser grids of the chain are cut from them), or null
   int32_t* cellOf;    // [n]
   int32_t* cellStart; // [n+1]
   int32_t* cellOf2;
@@ -480,7 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(Work W, int pass, int ntil
 // Cell runs.  mode 0: a new cell starts where the sorted key changes, and
 // the points are gathered into cell order (SoA).  mode 1 (only when some cell
 // failed the diameter guard): additionally every point of an unsafe cell becomes
-// a cell of its own, written to the second set of cell arrays.
+// a cell of its own, written to the second set of cell arrays.  mode 2: a grid
+// derived from a finer one (k_derive): the points keep their order and the cells
+// are the runs of equal kept keys (skey >> cell_key_shift).
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
@@ -494,8 +502,9 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
   const bool odd = (g->passes & 1) != 0;
   const uint64_t* keys = odd ? W.keyB : W.keyA;
   const uint32_t* idx = odd ? W.idxB : W.idxA;
-  int32_t* cof = mode ? W.cellOf2 : W.cellOf;
-  int32_t* cst = mode ? W.cellStart2 : W.cellStart;
+  // (mode 1 writes the second set of cell arrays; modes 0 and 2 the first)
+  int32_t* cof = mode == 1 ? W.cellOf2 : W.cellOf;
+  int32_t* cst = mode == 1 ? W.cellStart2 : W.cellStart;
   const int tid = threadIdx.x;
   if (tid == 0) s_tile = atomicAdd(&W.tilectr[8 + mode], 1);
   __syncthreads();
@@ -515,6 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
         h = true;
       } else if (mode == 0) {
         h = (keys[i] >> cks) != (keys[i - 1] >> cks);
+      } else if (mode == 2) {
+        h = (W.skey[i] >> cks) != (W.skey[i - 1] >> cks);
       } else {
         const int c = W.cellOf[i];
         h = c != W.cellOf[i - 1] || W.unsafe[c];
@@ -555,13 +566,41 @@ __global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
       cst[cid + 1] = n;
       W.desc->n_cells = cid + 1;
     }
+    if (mode == 2) W.cnt[i] = 0;  // MarkCore's waves add their shares to it (k_keys did not run)
     if (mode == 0) {
       uint32_t src = idx[i];
       if (src >= (uint32_t)n) src = 0;  // only after an expired wait
       W.perm[i] = (int32_t)src;
+      if (W.inv) W.inv[src] = i;
+      if (W.skey) W.skey[i] = keys[i];
 #pragma unroll
       for (int k = 0; k < D; ++k) W.X[(size_t)k * n + i] = W.pts[(size_t)src * D + k];
     }
+  }
+}
+
+// A grid for eps' = 2^j eps from the grid of eps of the same cloud (call
+// initialisation included, as k_bbox_partial does for a new grid).  With the same
+// origin and side s' = 2^j s, each cell index of the coarser grid is the finer one
+// divided by 2^j (scaling by a power of two is exact), so the coarser Morton key
+// is the finer key without its lowest j levels: those levels hold min(bits_k, j)
+// bits of each dimension k.  The points stay in the finer grid's order, which is
+// sorted by the coarser key too; k_cells mode 2 cuts the runs.  (Any cut is exact:
+// the diameter guard and the box tree decide every pair as for a fresh grid.)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_derive(Work W, int j) {
+  init_call(W, 0);
+  if (threadIdx.x == 0) {
+    GridDesc* g = W.desc;
+    int cut = 0;
+    for (int k = 0; k < D; ++k) {
+      const int b = g->bits[k];
+      cut += min(b, j);
+      g->bits[k] = max(0, b - j);
+    }
+    g->cell_key_shift += cut;
+    g->total_bits -= cut;
+    g->side = ldexp(g->side, j);
   }
 }
 
@@ -820,6 +859,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subsort(Work W) {
         if (ch * kWave >= b) continue;
         const int i = ch * kWave + lane;
         W.perm[i] = pm[v];
+        if (W.inv) W.inv[pm[v]] = i;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
           W.X[(size_t)k * n + i] = x[v][k];

@@ -18,6 +18,15 @@ def _batch(clouds, settings, mode):
     return binding.Batch([torch.from_numpy(X).to("cuda") for X in clouds], settings, mode=mode)
 
 
+def _mismatch(core, lab, want):
+    """A short description of how a result differs from the oracle's."""
+    bad = np.flatnonzero(lab != want[1])
+    wc = want[0].astype(bool)
+    return (f"{bad.size} labels differ ({int(wc[bad].sum())} at core points), first at "
+            f"{bad[:5].tolist()}: got {lab[bad[:5]].tolist()} want {want[1][bad[:5]].tolist()}; "
+            f"clusters got {len(np.unique(lab[core.astype(bool)]))} want {len(np.unique(want[1][wc]))}")
+
+
 def _check_batch(b, clouds, settings, tag):
     for i, (X, st) in enumerate(zip(clouds, settings)):
         for s, (eps, mp) in enumerate(st):
@@ -25,7 +34,8 @@ def _check_batch(b, clouds, settings, tag):
             core = b.core[i][s].cpu().numpy()
             lab = b.label[i][s].cpu().numpy()
             assert np.array_equal(core, want[0]), f"{tag}: cloud {i} setting {s} core"
-            assert np.array_equal(lab, want[1]), f"{tag}: cloud {i} setting {s} labels"
+            assert np.array_equal(lab, want[1]), \
+                f"{tag}: cloud {i} setting {s} labels: {_mismatch(core, lab, want)}"
 
 
 def _clouds():
@@ -114,6 +124,48 @@ def test_multi_cloud_batch_small(gpu_lib):
     b.run()
     b.run()
     _check_batch(b, clouds, settings, "multi-cloud")
+
+
+def _many_minpts_case():
+    rng = np.random.Generator(np.random.PCG64(411))
+    n = 30_000
+    A = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=412)
+    B = gaussian_mixture(4000, 5, 6, 1.0, 10.0, 0.05, rng)
+    # dense 2D blobs: cells of hundreds of points (sub-cell order from 256 points)
+    Cd = gaussian_mixture(20_000, 2, 3, 1.0, 10.0, 0.05, rng)
+    settings = [
+        # ten settings of one eps (more than one group of eight), a repeated minPts
+        [(200.0, m) for m in (3, 5, 8, 10, 15, 20, 30, 50, 100, 10)] + [(400.0, 5), (400.0, 50)],
+        [(1.5, m) for m in (2, 5, 10, 20)],
+        [(3.0, m) for m in (5, 50, 500, 1000)],
+    ]
+    return [A, B, Cd], settings
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
+@pytest.mark.parametrize("rounds", [-1, 1])
+def test_batch_many_minpts_per_eps(mode, rounds, gpu_lib):
+    """Settings of one eps share their grid: they are taken by decreasing minPts,
+    each ClusterCore starting from the union-find the previous one left, with the
+    core flags of all of them set at once and their outputs written together in
+    input order.  Covers more settings than one group holds, a repeated minPts, both
+    ClusterCore schedules (one pass, rounds), d = 2, 3, 5, and large cells in
+    sub-cell order (the inverse permutation of the outputs follows the regrouping)."""
+    from paper_1912_06255_amd import binding
+
+    clouds, settings = _many_minpts_case()
+    binding.set_option("bcp_rounds", rounds)
+    binding.set_option("subcell_min", 256)
+    try:
+        b = _batch(clouds, settings, mode)
+        log(f"many-minPts batch mode={mode} rounds={rounds}")
+        b.run()
+        _check_batch(b, clouds, settings, f"many minPts {mode} rounds={rounds}")
+        b.run()  # graph replay
+        _check_batch(b, clouds, settings, f"many minPts replay {mode} rounds={rounds}")
+    finally:
+        binding.set_option("bcp_rounds", -1)
+        binding.set_option("subcell_min", -1)
 
 
 def test_batch_invalid_arguments(gpu_lib):
