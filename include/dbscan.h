@@ -50,6 +50,7 @@ extern "C" {
 #define DBSCAN_EHIP (-3)       /* a HIP runtime call failed */
 #define DBSCAN_ENONFINITE (-4) /* a coordinate is NaN or infinite */
 #define DBSCAN_EINTERNAL (-5)  /* an internal bounded wait expired (should not happen) */
+#define DBSCAN_ETOOLARGE (-6)  /* dbscan_noalloc: the call needs more than its fixed scratch */
 
 #define DBSCAN_MAX_N 1073741823LL /* 2^30 - 1 points per call */
 #define DBSCAN_MAX_D 8
@@ -302,6 +303,36 @@ int dbscan_tune_clear(dbscan_ctx *ctx);
  */
 int dbscan_membership(dbscan_ctx *ctx, int64_t *offsets, int32_t *ids, int64_t ids_cap,
                       int64_t *total, void *stream);
+
+/*
+ * Allocation-free variant of dbscan(), for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same computation and outputs as dbscan() with the default
+ * options; no context is involved and no device memory is allocated or freed
+ * by the call (it calls no hipMalloc, hipFree or allocating routine).
+ *
+ * Its scratch is one file-scope device array of DBSCAN_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, held by each GPU the library runs on until the process
+ * ends.  The call runs on the calling thread's current device; its first call
+ * on a device looks up the array's address there.  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind, so calls that overlap on one
+ * GPU (other streams or threads) race and must not be issued; consecutive calls
+ * on one stream are fine.
+ *   points, n, d, eps, min_pts, mode, core_flags, cluster_id, stream
+ *                as for dbscan()
+ *   status       device uint32 or NULL: receives the call's DBSCAN_STATUS_*
+ *                bits (0 = fine; DBSCAN_STATUS_NONFINITE = a coordinate is NaN
+ *                or infinite, outputs undefined) when the stream reaches the
+ *                end of the call
+ * Limit: the call's scratch, about (80 + 37 d) bytes per point plus a few KiB,
+ * must fit the array: n up to 571,519 points in 1D, 351,744 in 3D and 179,332
+ * in 8D.  Larger inputs return DBSCAN_ETOOLARGE before any work is queued.
+ * Argument errors return DBSCAN_EINVAL as for dbscan().
+ */
+#define DBSCAN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dbscan_noalloc(const double *points, int64_t n, int32_t d, double eps, int32_t min_pts,
+                   int32_t mode, uint8_t *core_flags, int32_t *cluster_id, uint32_t *status,
+                   void *stream);
 
 /* Static description of a return code. */
 const char *dbscan_strerror(int code);

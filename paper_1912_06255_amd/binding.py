@@ -22,6 +22,7 @@ ENOMEM = -2
 EHIP = -3
 ENONFINITE = -4
 EINTERNAL = -5
+ETOOLARGE = -6
 
 OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4, "batch_graph": 5,
            "bcp_split": 6, "filter_max_d": 7, "subcell_min": 8}
@@ -131,12 +132,13 @@ def load():
     lib.dbscan_tune_load.argtypes = [vp, ctypes.c_char_p]
     lib.dbscan_tune_clear.argtypes = [vp]
     lib.dbscan_membership.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+    lib.dbscan_noalloc.argtypes = [vp, i64, i32, f64, i32, i32, vp, vp, vp, vp]
     lib.dbscan_strerror.argtypes = [ctypes.c_int]
     lib.dbscan_strerror.restype = ctypes.c_char_p
     for f in ("dbscan_ctx_create", "dbscan_ctx_destroy", "dbscan_reserve", "dbscan", "dbscan_get_stats",
               "dbscan_set_profiling", "dbscan_phase_times", "dbscan_phase_stats", "dbscan_set_option", "dbscan_get_option",
               "dbscan_batch", "dbscan_tune", "dbscan_tune_save", "dbscan_tune_load", "dbscan_tune_clear",
-              "dbscan_membership", "dbscan_approx"):
+              "dbscan_membership", "dbscan_approx", "dbscan_noalloc"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -224,6 +226,34 @@ def dbscan(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None,
     if check and n > 0:
         stats(dev, stream, raise_on_error=True)
     return core, label
+
+
+def dbscan_noalloc(points, eps: float, min_pts: int, mode="fp64", out=None, status=None,
+                   stream=None):
+    """dbscan() through the allocation-free entry point (fixed device scratch, no
+    context): for inputs within its size limit.  ``out`` (core, labels) and
+    ``status`` (int32 tensor of one element, receives the status bits) are CUDA
+    tensors supplied by the caller or allocated here.  Asynchronous."""
+    import torch
+
+    if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64
+            and points.dim() == 2):
+        raise TypeError("points must be a float64 CUDA tensor [n, d]")
+    points = points.contiguous()
+    n, d = points.shape
+    dev = points.device.index if points.device.index is not None else torch.cuda.current_device()
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.uint8, device=points.device),
+               torch.empty(n, dtype=torch.int32, device=points.device))
+    st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+    with torch.cuda.device(dev):
+        rc = load().dbscan_noalloc(
+            ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts), m,
+            ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()), st,
+            _stream_handle(dev, stream))
+    _check(rc, "dbscan_noalloc")
+    return out
 
 
 def tune(points, eps: float, min_pts: int, mode="fp64", out=None, stream=None) -> dict:

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -759,6 +760,93 @@ int check_call(const dbscan_ctx* ctx, const double* points, int64_t n, int32_t d
 
 }  // namespace
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free calls (dbscan_noalloc): the scratch of one call lives in a
+// file-scope device array of fixed size instead of a context's allocation.  Each
+// GPU holds its own copy of the array for the life of the process; host code
+// never uses the array's name (a host-side stand-in), only the device address
+// hipGetSymbolAddress returns, looked up once per device.  The array starts
+// zeroed (the code object's zero-filled segment), so the call descriptor at its
+// start begins with epoch 0 and no look-back word of an earlier call can match a
+// later call's epoch.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DBSCAN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+
+struct NoAllocSlot {
+  bool ready = false;
+  void* ptr = nullptr;  // device address of `scratch` on this device
+  dbscan_ctx ctx;       // default options, scratch = ptr (never grown)
+};
+
+NoAllocSlot g_noalloc[kNoAllocDevices];
+std::mutex g_noalloc_mu;
+
+// The call's status bits (0 for a call with no points: g == nullptr).
+__global__ void k_status_out(const GridDesc* g, uint32_t* out) {
+  if (threadIdx.x == 0) *out = g ? g->status : 0u;
+}
+
+// The slot of device dev, set up on its first use (dev current).
+int noalloc_slot(int dev, NoAllocSlot** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocSlot& S = g_noalloc[dev];
+  if (!S.ready) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DBSCAN_EHIP;
+    // the lookup may leave an error recorded for code objects it searched before
+    // finding the symbol; it succeeded, so that record is dropped
+    (void)hipGetLastError();
+    S.ptr = p;
+    S.ctx.device = dev;
+    S.ctx.desc_bytes = align_up(sizeof(GridDesc));
+    S.ctx.scratch = p;
+    S.ctx.scratch_bytes = DBSCAN_NOALLOC_SCRATCH_BYTES;
+    S.ctx.desc = reinterpret_cast<GridDesc*>(p);
+    S.ready = true;
+  }
+  *out = &S;
+  return DBSCAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbscan_noalloc(const double* points, int64_t n, int32_t d, double eps, int32_t min_pts,
+                   int32_t mode, uint8_t* core_flags, int32_t* cluster_id, uint32_t* status,
+                   void* stream) {
+  int rc = check_args(n, d, eps, min_pts);
+  if (rc != DBSCAN_OK) return rc;
+  if (mode != DBSCAN_PLAIN_FP64 && mode != DBSCAN_FP32_FILTER) return DBSCAN_EINVAL;
+  if (n > 0 && (!points || !core_flags || !cluster_id)) return DBSCAN_EINVAL;
+  if (align_up(sizeof(GridDesc)) + layout(nullptr, n, d, nullptr) > DBSCAN_NOALLOC_SCRATCH_BYTES)
+    return DBSCAN_ETOOLARGE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DBSCAN_EHIP;
+  if (dev < 0 || dev >= kNoAllocDevices) return DBSCAN_EINVAL;
+  NoAllocSlot* S = nullptr;
+  rc = noalloc_slot(dev, &S);
+  if (rc != DBSCAN_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n > 0) {
+    // the size check above keeps run_one's scratch growth a no-op: nothing is allocated
+    rc = run_one(&S->ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s,
+                 resolve(&S->ctx, n, d, mode));
+    if (rc != DBSCAN_OK) return rc;
+  }
+  if (status) {
+    if (n > 0) k_status_out<<<1, 64, 0, s>>>(S->ctx.desc, status);
+    else k_status_out<<<1, 64, 0, s>>>(nullptr, status);
+  }
+  return hipGetLastError() == hipSuccess ? DBSCAN_OK : DBSCAN_EHIP;
+}
+
 int dbscan(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double eps,
            int32_t min_pts, int32_t mode, uint8_t* core_flags, int32_t* cluster_id,
            void* stream) {
@@ -1195,6 +1283,7 @@ const char* dbscan_strerror(int code) {
     case DBSCAN_EHIP: return "HIP runtime error";
     case DBSCAN_ENONFINITE: return "non-finite coordinate";
     case DBSCAN_EINTERNAL: return "internal bounded wait expired";
+    case DBSCAN_ETOOLARGE: return "input exceeds the allocation-free scratch";
   }
   return "unknown error";
 }

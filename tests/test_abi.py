@@ -34,11 +34,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_strerror_covers_every_code(lib):
     seen = set()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         s = binding.strerror(code)
         assert s and s != "unknown error"
         seen.add(s)
-    assert len(seen) == 6
+    assert len(seen) == 7
     assert binding.strerror(-99) == "unknown error"
 
 
