@@ -177,8 +177,10 @@ int dbscan_get_stats(dbscan_ctx *ctx, void *stream, dbscan_stats *out);
 /*
  * Phase timing.  With profiling on, each call records HIP events on its stream
  * between its phases (grid box, keys, radix sort, cell runs, cell boxes and
- * guard, box tree, MarkCore, ClusterCore, relabel, ClusterBorder, output
- * scatter); a profiled dbscan_batch() runs eagerly (no graph) and records the
+ * guard, box tree, MarkCore counts, core flags, ClusterCore, relabel,
+ * ClusterBorder, output scatter, and ClusterCore of a setting started from the
+ * union-find of the previous one, timed apart); a profiled dbscan_batch() runs
+ * eagerly (no graph) and records the
  * same boundaries for every cloud and setting.  dbscan_phase_times()
  * synchronises `stream` and writes up to `cap` per-phase durations in
  * milliseconds of the last call, each summed over every occurrence of the phase
@@ -188,7 +190,7 @@ int dbscan_get_stats(dbscan_ctx *ctx, void *stream, dbscan_stats *out);
  * same and also writes the number of occurrences of each phase to
  * `occurrences` (may be NULL).
  */
-#define DBSCAN_NUM_PHASES 11
+#define DBSCAN_NUM_PHASES 13
 int dbscan_set_profiling(dbscan_ctx *ctx, int on);
 int dbscan_phase_times(dbscan_ctx *ctx, void *stream, float *ms, int32_t cap);
 int dbscan_phase_stats(dbscan_ctx *ctx, void *stream, float *ms, int32_t *occurrences,

@@ -755,57 +755,95 @@ struct MultiCore {
   int32_t* minIdx[kMultiMax];
 };
 
-__global__ __launch_bounds__(kBlock) void k_core_multi(Work W, MultiCore M) {
+// Per-cell starting values of k_core_multi (one thread per cell).
+__global__ void k_core_multi_init(Work W, MultiCore M) {
   const int C = W.desc->n_cells;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
-    const int s = W.cellStart[g], e = W.cellStart[g + 1];
-    int cc[kMultiMax], mn[kMultiMax];
-#pragma unroll
-    for (int t = 0; t < kMultiMax; ++t) {
-      cc[t] = 0;
-      mn[t] = kIntMax;
-    }
-    for (int i0 = s; i0 < e; i0 += 4 * kWave) {
-      int c[4], pm[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u * kWave + lane;
-        c[u] = i < e ? W.cnt[i] : -1;
-        pm[u] = i < e ? W.perm[i] : kIntMax;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u * kWave + lane;
-        uint32_t bits = 0;
-#pragma unroll
-        for (int t = 0; t < kMultiMax; ++t) {
-          const bool core = t < M.k && c[u] >= M.minPts[t];
-          bits |= core ? (1u << t) : 0u;
-          cc[t] += core ? 1 : 0;
-          mn[t] = core ? min(mn[t], pm[u]) : mn[t];
-        }
-        if (i < e) W.coreS[i] = (uint8_t)bits;
-      }
-    }
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < C; g += gridDim.x * blockDim.x) {
 #pragma unroll
     for (int t = 0; t < kMultiMax; ++t) {
       if (t >= M.k) break;
-      const int a = wave_sum(cc[t]), b = wave_min(mn[t]);
-      if (lane == 0) {
-        M.coreCount[t][g] = a;
-        M.cellMin[t][g] = b;
-        M.minIdx[t][g] = kIntMax;
+      M.coreCount[t][g] = 0;
+      M.cellMin[t][g] = kIntMax;
+      M.minIdx[t][g] = kIntMax;
+    }
+    if (!M.warm) W.parent[g] = g;
+  }
+}
+
+// One thread per sorted position: each wave takes a run of kCoreRun consecutive
+// 64-position chunks, so a large cell is spread over many waves instead of one.
+// Per setting, the core count and smallest core input index of each cell are
+// reduced over the wave's positions (kept across its chunks while the cell
+// continues) and added to the cell with one atomic each.
+constexpr int kCoreRun = 16;
+
+__global__ __launch_bounds__(kBlock) void k_core_multi(Work W, MultiCore M) {
+  const int n = W.n;
+  const int lane = lane_id();
+  const int nchunks = (n + kWave - 1) / kWave;
+  const int nruns = (nchunks + kCoreRun - 1) / kCoreRun;
+  for (int run = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; run < nruns;
+       run += gridDim.x * kWavesPerBlock) {
+    int cur = -1;  // cell of the running partials (wave-uniform)
+    int sum[kMultiMax], mn[kMultiMax];
+    auto flush = [&]() {
+      if (cur < 0 || lane != 0) return;
+#pragma unroll
+      for (int t = 0; t < kMultiMax; ++t) {
+        if (t >= M.k) break;
+        if (sum[t] > 0) {
+          atomicAdd(&M.coreCount[t][cur], sum[t]);
+          atomicMin(&M.cellMin[t][cur], mn[t]);
+        }
+      }
+    };
+    const int ch_end = min(nchunks, (run + 1) * kCoreRun);
+    for (int ch = run * kCoreRun; ch < ch_end; ++ch) {
+      const int i = ch * kWave + lane;
+      const bool valid = i < n;
+      const int c = valid ? W.cellOf[i] : -1;
+      const int cn = valid ? W.cnt[i] : -1;
+      const int pm = valid ? W.perm[i] : kIntMax;
+      uint32_t bits = 0;
+#pragma unroll
+      for (int t = 0; t < kMultiMax; ++t)
+        bits |= (t < M.k && cn >= M.minPts[t]) ? (1u << t) : 0u;
+      if (valid) {
+        W.coreS[i] = (uint8_t)bits;
+        W.pk[i] = ((uint64_t)c << 8) | bits;
+      }
+      // the cells of this chunk, in order (usually one or two)
+      for (uint64_t todo = ballot(valid); todo;) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int cc = __shfl(c, leader, kWave);
+        const bool mine = valid && c == cc;
+        if (cc != cur) {
+          flush();
+          cur = cc;
+#pragma unroll
+          for (int t = 0; t < kMultiMax; ++t) {
+            sum[t] = 0;
+            mn[t] = kIntMax;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kMultiMax; ++t) {
+          if (t >= M.k) break;
+          const bool core = mine && ((bits >> t) & 1u);
+          sum[t] += wave_sum(core ? 1 : 0);
+          mn[t] = min(mn[t], wave_min(core ? pm : kIntMax));
+        }
+        todo &= ~ballot(mine);
       }
     }
-    if (lane == 0 && !M.warm) W.parent[g] = g;
+    flush();
   }
 }
 
 // Outputs of the settings of one eps in input order: position j of every output
-// array is written by one thread (coalesced stores), which reads its sorted
-// position through the inverse permutation and the setting's cell label (core
-// points) or border label.
+// array is written by one thread (coalesced stores), which gathers its sorted
+// position's cell and core bits (one word, through the inverse permutation) and
+// then the setting's cell label (core points) or border label.
 struct MultiOut {
   int k;
   uint8_t* core[kMultiMax];
@@ -818,8 +856,9 @@ __global__ void k_output_multi(Work W, MultiOut O) {
   const int n = W.n;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const int i = W.inv[j];
-    const int c = W.cellOf[i];
-    const uint32_t bits = W.coreS[i];
+    const uint64_t v = W.pk[i];
+    const int c = (int)(v >> 8);
+    const uint32_t bits = (uint32_t)(v & 255u);
 #pragma unroll
     for (int t = 0; t < kMultiMax; ++t) {
       if (t >= O.k) break;
@@ -871,6 +910,7 @@ struct BcpVisitor {
   int c0, nchk;    // first aligned chunk of the unit and number of chunks
   int hmax;        // candidate cells are those with index < hmax
   int ucell;       // a core cell of the unit; links are made from it
+  bool one_cell;   // the unit is one cell (its anchor is uq.lo): float32 offsets need no loads
   int rg;          // a root of the unit's component (refreshed per group; stale is safe)
   Query<D> uq;     // box of the unit
   double* ub;      // [2 D][64] LDS: the unit's chunk boxes (lo, then hi), when it has <= 64
@@ -894,7 +934,7 @@ struct BcpVisitor {
       load_point<D>(W->X, W->n, i, x);
       if constexpr (F32) {
         load_local<D>(W->X32, W->n, i, a);
-        cell = W->cellOf[i];
+        if (!one_cell) cell = W->cellOf[i];
       }
       v = (core & W->core_mask) != 0;
     }
@@ -916,8 +956,9 @@ struct BcpVisitor {
   // unit's chunk cidx.  Unit points farther than eps from the box [blo, bhi], which
   // holds every valid q, drop out first.  Links the unit to h at the first pair
   // within eps and returns true.
+  // hoff: T = fl32(A_unit - A_h) when the unit is one cell (else unused).
   DB_DEV bool tile(int cidx, int h, const double (&xq)[D], const float (&aq)[D], bool valid,
-                   int q, const double (&blo)[D], const double (&bhi)[D]) {
+                   int q, const double (&blo)[D], const double (&bhi)[D], const float (&hoff)[D]) {
     const int lane = lane_id();
     const int chunk = c0 + cidx;
     double xp[D];
@@ -930,14 +971,14 @@ struct BcpVisitor {
     int curcell = -1;
     float off[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) off[d] = 0.0f;
+    for (int d = 0; d < D; ++d) off[d] = hoff[d];
     while (pm) {
       const int t = __ffsll((long long)pm) - 1;
       pm &= pm - 1;
       bool hit;
       ctr.pairs += (unsigned long long)__popcll(ballot(valid));
       if constexpr (F32) {
-        const int pc = bcast(pcell, t);
+        const int pc = one_cell ? -1 : bcast(pcell, t);
         if (pc != curcell) {
           curcell = pc;
           double apc[D];
@@ -1018,10 +1059,24 @@ struct BcpVisitor {
     return ballot(sv);
   }
 
+  // T = fl32(A_unit - A_h) for a one-cell unit (the same arithmetic as anchor_offsets)
+  DB_DEV void unit_offsets(const double (&ah)[D], float (&hoff)[D]) const {
+#pragma unroll
+    for (int d = 0; d < D; ++d) hoff[d] = F32 && one_cell ? (float)(uq.lo[d] - ah[d]) : 0.0f;
+  }
+
   DB_DEV bool dense_leaves(int h, int hs, int he) {
     const int lane = lane_id();
     const int cap = W->chunkCap;
     ensure_ub();
+    float hoff[D];
+    {
+      double ah[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) ah[d] = 0.0;
+      if (F32 && one_cell) load_anchor<D>(W->tree, h, ah);
+      unit_offsets(ah, hoff);
+    }
     const int hc0 = hs / kWave, hc1 = (he - 1) / kWave;
     for (int hw = hc0; hw <= hc1; hw += kWave) {
       const int hcl = hw + lane;
@@ -1044,7 +1099,7 @@ struct BcpVisitor {
         }
         for (int pc0 = 0; pc0 < nchk; pc0 += kWave)
           for (uint64_t sm = unit_mask(pc0, qlo, qhi); sm; sm &= sm - 1)
-            if (tile(pc0 + __ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi))
+            if (tile(pc0 + __ffsll((long long)sm) - 1, h, xq, aq, valid, q, qlo, qhi, hoff))
               return true;
       }
     }
@@ -1084,6 +1139,8 @@ struct BcpVisitor {
       } else {
         Query<D> hb;
         load_box<D>(W->tree, h, hb);
+        float hoff[D];
+        unit_offsets(hb.lo, hoff);
         for (int qb = hs; qb < he && !linked_h; qb += kWave) {
           double xq[D];
           float aq[D];
@@ -1091,7 +1148,7 @@ struct BcpVisitor {
           const bool valid = load_q(qb, hs, he, xq, aq, q);
           if (!ballot(valid)) continue;
           for (int cidx = 0; cidx < nchk && !linked_h; ++cidx)
-            linked_h = tile(cidx, h, xq, aq, valid, q, hb.lo, hb.hi);
+            linked_h = tile(cidx, h, xq, aq, valid, q, hb.lo, hb.hi, hoff);
         }
       }
       if (linked_h) {
@@ -1138,17 +1195,22 @@ struct BcpVisitor {
       bool valid = k < tot;
       int j = 0, q = 0;
       double xq[D];
-      float aq[D];
+      float aq[D], qoff[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         xq[d] = 0.0;
         aq[d] = 0.0f;
+        qoff[d] = 0.0f;
       }
       if (valid) {
         locate(F, k, j, q);
         const uint8_t core = W->coreS[q];
         load_point<D>(W->X, n, q, xq);
-        if constexpr (F32) load_local<D>(W->X32, n, q, aq);
+        if constexpr (F32) {
+          load_local<D>(W->X32, n, q, aq);
+          // a one-cell unit: T of this lane's cell, once for every unit chunk
+          if (one_cell) anchor_offsets<D>(W->tree, uq.lo, cb + j, qoff);
+        }
         // points of h farther than eps from the unit's box drop out
         valid = (core & W->core_mask) != 0 && ((alive >> j) & 1ull) &&
                 box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
@@ -1185,14 +1247,14 @@ struct BcpVisitor {
           int curcell = -1;
           float off[D];
 #pragma unroll
-          for (int d = 0; d < D; ++d) off[d] = 0.0f;
+          for (int d = 0; d < D; ++d) off[d] = qoff[d];
           while (pm) {
             const int t = __ffsll((long long)pm) - 1;
             pm &= pm - 1;
             bool hit;
             ctr.pairs += (unsigned long long)__popcll(ballot(valid));
             if constexpr (F32) {
-              const int pc = bcast(pcell, t);
+              const int pc = one_cell ? -1 : bcast(pcell, t);
               if (pc != curcell) {
                 curcell = pc;
                 double apc[D];
@@ -1243,7 +1305,9 @@ struct BcpVisitor {
 // acts as a single unit (its first cell's wave runs it), instead of each of its
 // cells repeating the same links.
 // round = -1: a single pass in which every core cell walks the whole tree.
-template <int D, bool F32>
+// WARM: the union-find starts from the previous setting's (see Work::warm); a
+// separate instantiation, so that the cold kernel keeps its register budget.
+template <int D, bool F32, bool WARM>
 // Four waves per SIMD where that fits without spilling (float64, d <= 4); the other
 // instantiations need more registers and would spill to scratch.
 __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, int round) {
@@ -1279,6 +1343,12 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
       if (W.nroot[l][idx] >= 0 && (l == umax || W.nroot[l + 1][g >> (6 * (l + 1))] < 0)) ulevel = l;
     }
     if (ulevel < 0) continue;
+    // Warm start with the previous setting's core counts: a link the union-find lacks
+    // needs a pair within eps with a point that was not core before (pairs of earlier
+    // core points were all linked), so only cells that gained core points act, and
+    // they test every neighbour cell, not only those of lower index.
+    const bool gained_only = WARM && W.prev_core_count != nullptr;
+    if (gained_only && W.coreCount[g] <= W.prev_core_count[g]) continue;
     BcpVisitor<D, F32> v;
     v.W = &W;
     v.F = Flat{s_pref[w], s_start[w]};
@@ -1287,10 +1357,11 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     v.uq.E2 = W.E2b;  // ClusterCore's radius (eps, or eps (1 + rho) when approximate)
     v.tin = W.desc->tinb;
     v.tout = W.desc->toutb;
+    v.one_cell = ulevel == 0;
     if (ulevel == 0) {
       v.ps = W.cellStart[g];
       v.pe = W.cellStart[g + 1];
-      v.hmax = g;
+      v.hmax = gained_only ? C : g;
       v.ucell = g;
       load_box<D>(W.tree, g, v.uq);
     } else {
@@ -1317,11 +1388,14 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, 
     }
     v.c0 = v.ps >> 6;
     v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
-    // a warm start prunes by the node roots taken before the launch from the start
-    v.rg = W.warm ? uf_find(W.parent, v.ucell) : v.ucell;
+    // a warm start prunes by the node roots taken before the launch from the start:
+    // the cell's parent is its root after most links (a full find here made the
+    // compiler spill the kernel's registers; the walk's groups refresh the root)
+    v.rg = WARM ? W.parent[v.ucell] : v.ucell;
     v.excl_level = round >= 1 ? round : -1;
     v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
-    v.prune = round >= 1 || W.warm != 0;
+    // (a warm start with known previous counts takes no node roots: see stage_cluster)
+    v.prune = (WARM && !gained_only) || round >= 1;
     const int anc_level = round < 0 ? top + 1 : round + 1;
     const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
     if (round < 0 && ulevel == 0)

@@ -77,6 +77,7 @@ struct Work {
   int sub_min;        // cells of at least this many points get sub-cell order (k_subsort); kIntMax: none
   int warm;           // ClusterCore starts from the union-find the previous setting left (a larger
                       // minPts of the same eps: its core points, hence its links, are a subset)
+  const int32_t* prev_core_count;  // warm: that setting's per-cell core counts (or null)
   uint32_t core_mask; // bit of this setting in coreS (settings of one eps share one byte per point)
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double E2;
@@ -103,6 +104,8 @@ struct Work {
   int chunkCap;
   int32_t* perm;      // sorted position -> input index
   int32_t* inv;       // input index -> sorted position (kept only when several settings share a grid)
+  uint64_t* pk;       // [n] with inv: cell << 8 | core bits of each sorted position (one word for
+                      // the output pass to gather)
   uint64_t* skey;     // [n] sorted keys of the finest grid of a chain of eps values that differ by
                       // powers of two (coarser grids of the chain are cut from them), or null
   int32_t* cellOf;    // [n]
@@ -902,8 +905,12 @@ __global__ void k_cell_safe(Work W) {
       if (e - s >= W.sub_min && e / kWave - (s + kWave - 1) / kWave >= 2)
         W.sublist[atomicAdd(&g->n_sub, 1)] = s;
     }
+    // the extent bounds |coordinate - anchor| in the float32 filter; a cell that
+    // fails the guard becomes singletons, whose anchors are the points themselves
+    if (!uns) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
+      for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
+    }
   }
   bad = wave_sum(bad);
   ext = wave_max(ext);

@@ -58,6 +58,7 @@ def test_step_bytes_model():
     # grid phases once per eps, the others once per setting
     assert bench.phase_algorithmic_bytes("keys", items, True) == 2 * 1000 * (8 * 3 + 12)
     assert bench.phase_algorithmic_bytes("cluster_core", items, True) == 3 * 1000 * (4 * 3 + 1)
+    assert bench.phase_algorithmic_bytes("markcore", items, True) == 2 * 1000 * (4 * 3 + 4)
 
 
 def test_spatial_crop_keeps_density():

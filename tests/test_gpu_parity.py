@@ -116,6 +116,22 @@ def test_unsafe_cells_split(d, eps, mode, gpu_lib):
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
+def test_filter_band_ignores_split_cells(gpu_lib):
+    """Coarsened keys make every cell unsafe: all are split into single points, whose
+    anchors are the points themselves, so the float32 filter keeps its narrow band
+    (the extent of a split cell must not widen it) and rechecks stay rare."""
+    rng = np.random.Generator(np.random.PCG64(215))
+    blob = rng.normal(0.0, 1.5, size=(5_000, 2))
+    X = np.concatenate([blob, [[1e30, 1e30], [-1e30, 2e30]]])
+    (got, st) = gpu_dbscan(X, 1.0, 5, mode="fp32_filter", tag="split cells band", want_stats=True)
+    want = dbscan_brute(X, 1.0, 5)  # (the bucket oracle does not take extents of 1e30)
+    assert st["key_shift"] > 0 and st["n_unsafe"] >= 1, st
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    assert np.isfinite(st["filter_tin"]) and np.isfinite(st["filter_tout"]), st
+    assert (st["filter_tout"] - st["filter_tin"]) < 1e-5, st
+    assert st["pair_tests"] > 0 and st["fp64_rechecks"] * 100 <= st["pair_tests"], st
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_unsafe_split_with_sub_cell_order(mode, gpu_lib):
     """An unsafe cell first in cell order (its split renumbers every later cell)
