@@ -9,16 +9,15 @@ Cases (names say workload, size, eps and minPts):
 
 * the 2D blobs and the 1M-point 3D spreader;
 * both 2M-point mixtures (5D and 7D) at eps 1.5, 2 and 3;
-* the 10M-point 3D sweep cloud at eps 200, 400 and 800 for every minPts of the
-  sweep (about 2, 5.5 and 22 minutes per setting; at eps 1600 the oracle's
-  candidate scans, of order 1e13 pair tests, are beyond it);
+* the 10M-point 3D sweep cloud at every eps and minPts of the sweep (about 2, 5.5,
+  13 and 35 minutes per setting at eps 200, 400, 800 and 1600);
 * every cloud of the 256-cloud batch (one record holding one hash per cloud).
 
 The file is updated case by case, so a long run can be split (``--only PREFIX``)
 and resumed (cases already present are skipped unless ``--redo``).
 
-Run:  python tests/golden/make_full_size_hashes.py   (about two and a half hours on
-8 cores, most of it the sweep cloud at eps 800)
+Run:  python tests/golden/make_full_size_hashes.py   (about four hours on 8 cores,
+most of it the sweep cloud at eps 800 and 1600)
 """
 
 from __future__ import annotations
@@ -71,7 +70,7 @@ CASES = [
 for _d, _inst in ((5, 0), (7, 1)):
     for _e in (1.5, 2.0, 3.0):
         CASES.append((f"mixture{_d}d_n2000000_eps{_eps_name(_e)}_mp10", 2, _inst, 1.0, _e, 10))
-for _e in (200.0, 400.0, 800.0):
+for _e in (200.0, 400.0, 800.0, 1600.0):
     for _m in (5, 10, 50, 100):
         CASES.append((f"sweep3d_n10000000_eps{_eps_name(_e)}_mp{_m}", 3, 0, 1.0, _e, _m))
 
