@@ -231,6 +231,12 @@ const char *dbscan_phase_name(int32_t phase);
  *                          value; above it they decide in float64 directly
  *                          (0..8; -1: automatic = 3, the default).  Results
  *                          are the same either way.
+ *   DBSCAN_OPT_SPARSE      MarkCore, ClusterCore and ClusterBorder with the
+ *                          points of 64 consecutive sorted positions batched per
+ *                          tree walk, instead of one wave and one walk per cell.
+ *                          1: always; 0 or -1 (automatic, the default): never
+ *                          (the batched kernels measured slower on every grid
+ *                          tried).  Results are the same either way.
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -241,6 +247,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_BCP_SPLIT 6
 #define DBSCAN_OPT_FILTER_MAX_D 7
 #define DBSCAN_OPT_SUBCELL_MIN 8
+#define DBSCAN_OPT_SPARSE 9
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

@@ -33,6 +33,10 @@ DB_DEV int leaf_min(const Work& W) {
 #define DB_MARK_SPLIT 4
 #endif
 constexpr int kMarkSplit = DB_MARK_SPLIT;
+// Sparse grids (sparse.hpp): MarkCore, ClusterCore and ClusterBorder can instead batch
+// the points of consecutive cells per tree walk (Work::sparse_mode 1, chosen by the
+// host; the per-cell kernels below are then not launched).
+
 // Smallest segment of a ClusterCore unit handled by a wave of its own.
 #ifndef DB_BCP_SEGMENT
 #define DB_BCP_SEGMENT 192

@@ -17,6 +17,7 @@
 #include "../../include/dbscan.h"
 #include "cluster.hpp"
 #include "membership.hpp"
+#include "sparse.hpp"
 
 using namespace db;
 
@@ -63,6 +64,8 @@ struct dbscan_ctx {
   int bcp_split = -1;   // -1: automatic (1)
   int filter_max_d = -1;  // -1: automatic (3)
   int subcell_min = -1;   // -1: automatic (kSubMinAuto for d <= 3), 0: never
+  int sparse = -1;        // -1: automatic (never: slower on every workload measured),
+                          // 0: never, 1: always
   // autotuner: choices per (d, mode, size class), used where an option is automatic
   std::vector<TunedEntry> tuned;
   uint32_t tune_gen = 0;
@@ -305,8 +308,11 @@ void stage_grid_back(const Work& W, hipStream_t s, const Marks& mark, double eps
 
 template <int D, bool F32>
 void stage_count(const Work& W, hipStream_t s, const Marks& mark) {
-  k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192),
-                        kBlock, 0, s>>>(W);
+  if (W.sparse_mode != 1)
+    k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192),
+                          kBlock, 0, s>>>(W);
+  if (W.sparse_mode != 0)
+    k_markcore_sparse<D, F32><<<grid_for(ceil_div(W.n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
   mark(7);
 }
 
@@ -330,7 +336,9 @@ void stage_cluster(const Work& W, hipStream_t s, const Marks& mark, bool rounds)
     if (W.warm) k_bcp<D, F32, true><<<gb, kBlock, 0, s>>>(W, round);
     else k_bcp<D, F32, false><<<gb, kBlock, 0, s>>>(W, round);
   };
-  if (!rounds || (W.warm && W.prev_core_count)) {
+  if (W.sparse_mode == 1) {
+    // batched sparse kernel only
+  } else if (!rounds || (W.warm && W.prev_core_count)) {
     // (with the previous counts only cells that gained core points act, and they
     // need no subtree pruning: the node roots are not taken)
     if (W.warm && !W.prev_core_count) node_roots();
@@ -341,11 +349,18 @@ void stage_cluster(const Work& W, hipStream_t s, const Marks& mark, bool rounds)
       bcp(round);
     }
   }
+  if (W.sparse_mode != 0) {
+    const unsigned gn = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
+    if (W.warm) k_bcp_sparse<D, F32, true><<<gn, kBlock, 0, s>>>(W);
+    else k_bcp_sparse<D, F32, false><<<gn, kBlock, 0, s>>>(W);
+  }
   mark(W.warm ? kPhaseClusterWarm + 1 : 9);
   k_relabel_min<<<gc, kBlock, 0, s>>>(W);
   k_cell_label<<<gp, kBlock, 0, s>>>(W);
   mark(10);
-  k_border<D, F32><<<gw, kBlock, 0, s>>>(W);
+  if (W.sparse_mode != 1) k_border<D, F32><<<gw, kBlock, 0, s>>>(W);
+  if (W.sparse_mode != 0)
+    k_border_sparse<D, F32><<<grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(W);
   mark(11);
 }
 
@@ -449,6 +464,7 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.warm = 0;
   W.prev_core_count = nullptr;
   W.core_mask = 1u;
+  W.sparse_mode = ctx->sparse == 1 ? 1 : 0;
   layout(static_cast<char*>(ctx->scratch) + ctx->desc_bytes, n, d, &W, slots, keep_keys);
 }
 
@@ -631,6 +647,7 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->tune_gen);
   put(k, ctx->filter_max_d);
   put(k, ctx->subcell_min);
+  put(k, ctx->sparse);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -1236,6 +1253,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value < -1 || value == 1 || value > kIntMax) return DBSCAN_EINVAL;
       ctx->subcell_min = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_SPARSE:
+      if (value < -1 || value > 1) return DBSCAN_EINVAL;
+      ctx->sparse = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -1251,6 +1272,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_BCP_SPLIT: *value = ctx->bcp_split; return DBSCAN_OK;
     case DBSCAN_OPT_FILTER_MAX_D: *value = ctx->filter_max_d; return DBSCAN_OK;
     case DBSCAN_OPT_SUBCELL_MIN: *value = ctx->subcell_min; return DBSCAN_OK;
+    case DBSCAN_OPT_SPARSE: *value = ctx->sparse; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

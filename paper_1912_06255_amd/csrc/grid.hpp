@@ -78,6 +78,7 @@ struct Work {
   int warm;           // ClusterCore starts from the union-find the previous setting left (a larger
                       // minPts of the same eps: its core points, hence its links, are a subset)
   const int32_t* prev_core_count;  // warm: that setting's per-cell core counts (or null)
+  int sparse_mode;    // 0: per-cell kernels, 1: batched sparse kernels
   uint32_t core_mask; // bit of this setting in coreS (settings of one eps share one byte per point)
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double E2;

@@ -102,3 +102,21 @@ def test_approx_extreme_dimensions(d, mode, gpu_lib):
         core, lab = _approx(X, eps, 8, rho, mode)
         fails = check_approx(X, eps, 8, rho, core, lab)
         assert not fails, f"d={d} rho={rho}: {fails}"
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("rho", [0.1, 0.5])
+def test_approx_through_sparse_kernels(rho, mode, gpu_lib):
+    """ClusterCore at radius eps (1 + rho) in the batched sparse kernels (forced on
+    for 2D and 3D clouds), checked against the relaxed definition."""
+    from paper_1912_06255_amd import binding
+
+    for case in (0, 3):
+        name, X, eps, mp = CASES[case]
+        binding.set_option("sparse", 1)
+        try:
+            core, lab = _approx(X, eps, mp, rho, mode)
+        finally:
+            binding.set_option("sparse", -1)
+        fails = check_approx(X, eps, mp, rho, core, lab)
+        assert not fails, f"{name} sparse rho={rho}: {fails}"

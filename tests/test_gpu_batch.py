@@ -143,8 +143,8 @@ def _many_minpts_case():
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_filter"])
-@pytest.mark.parametrize("rounds", [-1, 1])
-def test_batch_many_minpts_per_eps(mode, rounds, gpu_lib):
+@pytest.mark.parametrize("rounds,sparse", [(-1, -1), (1, -1), (-1, 1), (1, 1)])
+def test_batch_many_minpts_per_eps(mode, rounds, sparse, gpu_lib):
     """Settings of one eps share their grid: they are taken by decreasing minPts,
     each ClusterCore starting from the union-find the previous one left, with the
     core flags of all of them set at once and their outputs written together in
@@ -156,16 +156,19 @@ def test_batch_many_minpts_per_eps(mode, rounds, gpu_lib):
     clouds, settings = _many_minpts_case()
     binding.set_option("bcp_rounds", rounds)
     binding.set_option("subcell_min", 256)
+    binding.set_option("sparse", sparse)
+    tag = f"{mode} rounds={rounds} sparse={sparse}"
     try:
         b = _batch(clouds, settings, mode)
-        log(f"many-minPts batch mode={mode} rounds={rounds}")
+        log(f"many-minPts batch {tag}")
         b.run()
-        _check_batch(b, clouds, settings, f"many minPts {mode} rounds={rounds}")
+        _check_batch(b, clouds, settings, f"many minPts {tag}")
         b.run()  # graph replay
-        _check_batch(b, clouds, settings, f"many minPts replay {mode} rounds={rounds}")
+        _check_batch(b, clouds, settings, f"many minPts replay {tag}")
     finally:
         binding.set_option("bcp_rounds", -1)
         binding.set_option("subcell_min", -1)
+        binding.set_option("sparse", -1)
 
 
 def test_batch_invalid_arguments(gpu_lib):

@@ -363,7 +363,9 @@ def test_sub_cell_order_exact_boundaries(opts, mode, gpu_lib):
 @pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
                                   dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
                                   dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=1),
-                                  dict(bcp_split=4), dict(bcp_split=2, bcp_rounds=1)])
+                                  dict(bcp_split=4), dict(bcp_split=2, bcp_rounds=1),
+                                  dict(sparse=0, bcp_rounds=1, unit_level=2),
+                                  dict(sparse=0, bcp_rounds=0), dict(sparse=1)])
 @pytest.mark.parametrize("mode", MODES)
 def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
     n = 40_000
@@ -377,7 +379,7 @@ def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
         gx = gpu_dbscan(X, 200.0, 10, mode=mode, tag=f"opts {opts} 3d")
         gy = gpu_dbscan(Y, 2.0, 10, mode=mode, tag=f"opts {opts} 5d")
     finally:
-        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1)
+        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1, sparse=-1)
     assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
     assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
 
@@ -388,7 +390,7 @@ def test_option_ranges(gpu_lib):
 
     bad = {"bcp_rounds": [2, -2], "unit_level": [-2, 6], "fine_bits": [-2, 9],
            "force_recheck": [2], "batch_graph": [-1], "bcp_split": [0, 65],
-           "filter_max_d": [-2, 9], "subcell_min": [-2, 1]}
+           "filter_max_d": [-2, 9], "subcell_min": [-2, 1], "sparse": [-2, 2]}
     for name, values in bad.items():
         before = binding.get_option(name)
         for v in values:
@@ -398,3 +400,28 @@ def test_option_ranges(gpu_lib):
     binding.set_option("subcell_min", 2)
     assert binding.get_option("subcell_min") == 2
     binding.set_option("subcell_min", -1)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("sparse", [0, 1])
+@pytest.mark.parametrize("d", [2, 3, 5, 7])
+def test_sparse_kernels_match_oracle(d, sparse, mode, gpu_lib):
+    """MarkCore, ClusterCore and ClusterBorder batched over 64 consecutive cells per
+    tree walk (sparse = 1) and one cell per wave (sparse = 0), on the same clouds:
+    eps small against the spread (about one point per cell) and larger (tens of
+    points per cell), with ragged sizes and noise; the float32 filter takes the
+    decisions in every dimension in filter mode."""
+    rng = np.random.Generator(np.random.PCG64(910 + d))
+    n = {2: 7001, 3: 9003, 5: 6007, 7: 5003}[d]
+    X = gaussian_mixture(n, d, 12, 1.0, 15.0, 0.05, rng)
+    cases = [(0.45, 3), (0.45, 10), (1.6, 10)] if d <= 3 else [(1.0, 5), (2.0, 10), (3.0, 20)]
+    try:
+        _set_opts(sparse=sparse, filter_max_d=8)
+        for eps, mp in cases:
+            (got, st) = gpu_dbscan(X, eps, mp, mode=mode, tag=f"sparse={sparse} d={d} eps={eps}",
+                                   want_stats=True)
+            want = dbscan_o1(X, eps, mp)
+            assert np.array_equal(got[0], want[0]), (d, eps, mp, "core")
+            assert np.array_equal(got[1], want[1]), (d, eps, mp, "labels")
+    finally:
+        _set_opts(sparse=-1, filter_max_d=-1)
