@@ -334,6 +334,12 @@ def extra_workload(name, dev, steps, warmup, filter_max_d=None):
                "fp64_rechecks_batch": st["fp64_rechecks"]}
         if filter_max_d is not None:
             rec["filter_max_d"] = filter_max_d
+            # the default choice for comparison: float64 decisions above 3 dimensions
+            binding.set_option("filter_max_d", -1)
+            b2, v2, ms2, _, _ = batched_rate(clouds, settings, "fp32_filter", points, steps, warmup)
+            del b2
+            rec["batched_default"] = {"value": v2, "ms_per_step": ms2, "filter_max_d": -1}
+            binding.set_option("filter_max_d", filter_max_d)
             per_eps = []
             X, st0, o0 = clouds[0], settings[0], outs[0]
             for (eps, mp), out in zip(st0, o0):
@@ -522,8 +528,12 @@ def main() -> int:
                 continue
             k = max(1, min(args.steps, 5))
             extra[name] = extra_workload(name, dev, k, 1, filter_max_d=fmd)
-            print(f"[bench] {name}: batched {extra[name]['batched_filter']['ms_per_step']:.2f} ms/step",
-                  file=sys.stderr, flush=True)
+            e = extra[name]
+            msg = (f"[bench] {name}: plain {e['plain_fp64']['ms_per_step']:.2f}, batched "
+                   f"{e['batched_filter']['ms_per_step']:.2f} ms/step")
+            if "batched_default" in e:
+                msg += f" (float64 decisions: {e['batched_default']['ms_per_step']:.2f})"
+            print(msg, file=sys.stderr, flush=True)
         out["other_workloads"] = extra
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(items)
     print(json.dumps(out), flush=True)

@@ -237,6 +237,16 @@ const char *dbscan_phase_name(int32_t phase);
  *                          1: always; 0 or -1 (automatic, the default): never
  *                          (the batched kernels measured slower on every grid
  *                          tried).  Results are the same either way.
+ *   DBSCAN_OPT_GROUP_CLOUDS  dbscan_batch() only: instances with a single setting
+ *                          and the same dimension (and options) form a group
+ *                          whose grids share every kernel launch, each grid
+ *                          keeping its own arrays (the batch's scratch grows by
+ *                          the sum of their sizes).  -1 (automatic, the
+ *                          default): groups of at least two instances, in more
+ *                          than 3 dimensions only of instances of at most 2^17
+ *                          points; 1: every such instance, alone or not, of any
+ *                          size; 0: never (one chain of launches per instance).
+ *                          Results are the same either way.
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -248,6 +258,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_FILTER_MAX_D 7
 #define DBSCAN_OPT_SUBCELL_MIN 8
 #define DBSCAN_OPT_SPARSE 9
+#define DBSCAN_OPT_GROUP_CLOUDS 10
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

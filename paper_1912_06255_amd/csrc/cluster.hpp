@@ -33,6 +33,10 @@ DB_DEV int leaf_min(const Work& W) {
 #define DB_MARK_SPLIT 4
 #endif
 constexpr int kMarkSplit = DB_MARK_SPLIT;
+// ... when the grid holds at least this many points per cell on average.  In
+// sparser grids every split wave would repeat a walk that finds little to share
+// (3D clouds of 1.5 points per cell: 84 -> 17.5 ms of MarkCore with one wave).
+constexpr int kMarkSplitMean = 32;
 // Sparse grids (sparse.hpp): MarkCore, ClusterCore and ClusterBorder can instead batch
 // the points of consecutive cells per tree walk (Work::sparse_mode 1, chosen by the
 // host; the per-cell kernels below are then not launched).
@@ -225,17 +229,21 @@ DB_DEV void node_lists_part(const Work& W, int nwg, int bid) {
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_node_lists(Work W) {
-  node_lists_part<D>(W, (int)gridDim.x, (int)blockIdx.x);
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_node_lists(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    node_lists_part<D>(W, (int)gridDim.x, (int)blockIdx.x);
+  });
 }
 
 // Node lists and the float32 coordinates in one launch (independent jobs): the
 // first nbl workgroups build the lists, the others convert the coordinates.
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_lists_local32(Work W, double eps, int nbl) {
-  if ((int)blockIdx.x < nbl) node_lists_part<D>(W, nbl, (int)blockIdx.x);
-  else local32_part<D>(W, eps, (int)gridDim.x - nbl, (int)blockIdx.x - nbl);
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_lists_local32(WS ws, int nbl) {
+  ws.each_wave([&](const Work& W) {
+    if ((int)blockIdx.x < nbl) node_lists_part<D>(W, nbl, (int)blockIdx.x);
+    else local32_part<D>(W, W.eps, (int)gridDim.x - nbl, (int)blockIdx.x - nbl);
+  });
 }
 
 // The walk of cell g from its node's list (or from the root if the list overflowed).
@@ -471,7 +479,7 @@ struct MarkCoreVisitor {
   int g, ps, pm;
   int cnt;           // lane t: count of point ps + t (|g| plus this wave's share)
   uint64_t pending;  // points of the batch still below minPts
-  int split, part;   // this wave tests every split-th candidate chunk, from part
+  int smask, part;   // this wave tests every (smask + 1)-th candidate chunk, from part
   int chunk_no;
   double p[D];       // lane t: coordinates of point ps + t (float64 mode)
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
@@ -492,7 +500,7 @@ struct MarkCoreVisitor {
     for (int d = 0; d < D; ++d) off[d] = 0.0f;
     if constexpr (F32) anchor_offsets<D>(W->tree, ag, h, off);
     for (int ch = hs / kWave; ch <= (he - 1) / kWave; ++ch) {
-      if (chunk_no++ % split != part) continue;
+      if ((chunk_no++ & smask) != part) continue;
       const int b0 = max(hs, ch * kWave), b1 = min(he, ch * kWave + kWave);
       bool test = false;
       if ((pending >> lane) & 1ull) {
@@ -585,7 +593,7 @@ struct MarkCoreVisitor {
     }
     const int tot = flatten_ranges(F, rcs, big ? 0 : rcn);
     for (int base = 0; base < tot; base += kWave) {
-      if (chunk_no++ % split != part) continue;
+      if ((chunk_no++ & smask) != part) continue;
       const int k = base + lane;
       const bool valid = k < tot;
       int j = 0, q = 0;
@@ -637,112 +645,122 @@ struct MarkCoreVisitor {
 // Neighbour counts, capped at count_cap (the largest minPts run with this eps, so
 // that one count serves every minPts).  A cell with at least count_cap points
 // needs no test: all its points are pairwise within eps.
-template <int D, bool F32>
-__global__ __launch_bounds__(kBlock) void k_markcore(Work W) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
-  __shared__ int s_order[kWavesPerBlock][kWave];
-  const int C = W.desc->n_cells;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int n = W.n;
-  const int cap = W.count_cap;
-  // Waves per cell: the candidate chunks of a cell's walk are dealt out to split
-  // waves, which add their counts (cnt is zeroed by k_keys); a wave stops when its
-  // own share reaches the cap, so every count is exact or at least the cap.
-  constexpr int split = D <= 3 ? kMarkSplit : 1;
-  Counters tot;
-  const UnitRange R = xcd_units((long long)C * split);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int g = (int)(u / split);
-    const int part = (int)(u % split);
-    const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
-    if (m >= cap) {
-      if (part == 0)
-        for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
-      continue;
-    }
-    Query<D> q;
-    q.E2 = W.E2;
-    load_box<D>(W.tree, g, q);
-    for (int ps = s; ps < e; ps += kWave) {
-      MarkCoreVisitor<D, F32> v;
-      v.W = &W;
-      v.F = Flat{s_pref[w], s_start[w]};
-      v.order = s_order[w];
-      v.g = g;
-      v.ps = ps;
-      v.pm = min(kWave, e - ps);
-      v.cnt = m;
-      v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
-      v.split = split;
-      v.part = part;
-      v.chunk_no = 0;
-      v.tin = W.desc->tin;
-      v.tout = W.desc->tout;
+template <int D, bool F32, class WS>
+// four waves per SIMD up to 3 dimensions (without the bound the float32
+// instantiation settles one register above that limit)
+__global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
+    __shared__ int s_order[kWavesPerBlock][kWave];
+    const int C = W.desc->n_cells;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int n = W.n;
+    const int cap = W.count_cap;
+    // Waves per cell: the candidate chunks of a cell's walk are dealt out to split
+    // waves, which add their counts (cnt is zeroed by k_keys); a wave stops when its
+    // own share reaches the cap, so every count is exact or at least the cap.
+    static_assert((kMarkSplit & (kMarkSplit - 1)) == 0, "split must be a power of two");
+    const int sh =
+        (D <= 3 && (long long)n >= (long long)kMarkSplitMean * C) ? __builtin_ctz(kMarkSplit) : 0;
+    const int split = 1 << sh;
+    Counters tot;
+    const UnitRange R = xcd_units((long long)C << sh);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int g = (int)(u >> sh);
+      const int part = (int)(u & (split - 1));
+      const int s = W.cellStart[g], e = W.cellStart[g + 1], m = e - s;
+      if (m >= cap) {
+        if (part == 0)
+          for (int i = s + lane; i < e; i += kWave) W.cnt[i] = m;
+        continue;
+      }
+      Query<D> q;
+      q.E2 = W.E2;
+      load_box<D>(W.tree, g, q);
+      for (int ps = s; ps < e; ps += kWave) {
+        MarkCoreVisitor<D, F32> v;
+        v.W = &W;
+        v.F = Flat{s_pref[w], s_start[w]};
+        v.order = s_order[w];
+        v.g = g;
+        v.ps = ps;
+        v.pm = min(kWave, e - ps);
+        v.cnt = m;
+        v.pending = v.pm == kWave ? ~0ull : ((1ull << v.pm) - 1ull);
+        v.smask = split - 1;
+        v.part = part;
+        v.chunk_no = 0;
+        v.tin = W.desc->tin;
+        v.tout = W.desc->tout;
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        v.p[d] = 0.0;
-        v.ap[d] = 0.0f;
+        for (int d = 0; d < D; ++d) {
+          v.p[d] = 0.0;
+          v.ap[d] = 0.0f;
+        }
+        v.lm = D <= 3 ? leaf_min(W) : kIntMax;
+        if (lane < v.pm) {
+          if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
+          if (!F32 || v.lm != kIntMax) load_point<D>(W.X, n, ps + lane, v.p);
+        }
+        if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
+        walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
+        if (lane < v.pm) {
+          if (split == 1) W.cnt[ps + lane] = v.cnt;
+          else atomicAdd(&W.cnt[ps + lane], part == 0 ? v.cnt : v.cnt - m);
+        }
+        tot.add(v.ctr);
       }
-      v.lm = D <= 3 ? leaf_min(W) : kIntMax;
-      if (lane < v.pm) {
-        if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
-        if (!F32 || v.lm != kIntMax) load_point<D>(W.X, n, ps + lane, v.p);
-      }
-      if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
-      if (lane < v.pm) {
-        if (split == 1) W.cnt[ps + lane] = v.cnt;
-        else atomicAdd(&W.cnt[ps + lane], part == 0 ? v.cnt : v.cnt - m);
-      }
-      tot.add(v.ctr);
     }
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 // Core flags of one minPts from the counts (Algorithm 2's test), the number of
 // core points and the smallest input index among them per cell, and the
 // union-find initialisation.
-__global__ __launch_bounds__(kBlock) void k_core_from_count(Work W) {
-  const int C = W.desc->n_cells;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
-    const int s = W.cellStart[g], e = W.cellStart[g + 1];
-    int cc = 0, mn = kIntMax;
-    // 8 x 64 points per step, all loads issued before any is used: a large cell
-    // costs a few load latencies instead of one per 64 points
-    for (int i0 = s; i0 < e; i0 += 8 * kWave) {
-      int c[8], pm[8];
+template <class WS>
+__global__ __launch_bounds__(kBlock) void k_core_from_count(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    const int C = W.desc->n_cells;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    for (int g = blockIdx.x * kWavesPerBlock + w; g < C; g += gridDim.x * kWavesPerBlock) {
+      const int s = W.cellStart[g], e = W.cellStart[g + 1];
+      int cc = 0, mn = kIntMax;
+      // 8 x 64 points per step, all loads issued before any is used: a large cell
+      // costs a few load latencies instead of one per 64 points
+      for (int i0 = s; i0 < e; i0 += 8 * kWave) {
+        int c[8], pm[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * kWave + lane;
-        c[u] = i < e ? W.cnt[i] : -1;
-        pm[u] = i < e ? W.perm[i] : kIntMax;
-      }
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * kWave + lane;
+          c[u] = i < e ? W.cnt[i] : -1;
+          pm[u] = i < e ? W.perm[i] : kIntMax;
+        }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * kWave + lane;
-        const bool core = c[u] >= W.minPts;
-        if (i < e) W.coreS[i] = core ? 1 : 0;
-        if (core) {
-          ++cc;
-          mn = min(mn, pm[u]);
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * kWave + lane;
+          const bool core = c[u] >= W.minPts;
+          if (i < e) W.coreS[i] = core ? 1 : 0;
+          if (core) {
+            ++cc;
+            mn = min(mn, pm[u]);
+          }
         }
       }
+      cc = wave_sum(cc);
+      mn = wave_min(mn);
+      if (lane == 0) {
+        W.coreCount[g] = cc;
+        W.cellMin[g] = mn;
+        W.parent[g] = g;
+        W.minIdx[g] = kIntMax;
+      }
     }
-    cc = wave_sum(cc);
-    mn = wave_min(mn);
-    if (lane == 0) {
-      W.coreCount[g] = cc;
-      W.cellMin[g] = mn;
-      W.parent[g] = g;
-      W.minIdx[g] = kIntMax;
-    }
-  }
+  });
 }
 
 // The settings of one eps (up to kMultiMax, by decreasing minPts) from the one
@@ -859,7 +877,8 @@ struct MultiOut {
 __global__ void k_output_multi(Work W, MultiOut O) {
   const int n = W.n;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const int i = W.inv[j];
+    int i = W.inv[j];
+    if ((unsigned)i >= (unsigned)n) i = 0;  // only if the sort failed (its status says so)
     const uint64_t v = W.pk[i];
     const int c = (int)(v >> 8);
     const uint32_t bits = (uint32_t)(v & 255u);
@@ -1311,130 +1330,135 @@ struct BcpVisitor {
 // round = -1: a single pass in which every core cell walks the whole tree.
 // WARM: the union-find starts from the previous setting's (see Work::warm); a
 // separate instantiation, so that the cold kernel keeps its register budget.
-template <int D, bool F32, bool WARM>
+template <int D, bool F32, bool WARM, class WS>
 // Four waves per SIMD where that fits without spilling (float64, d <= 4); the other
 // instantiations need more registers and would spill to scratch.
-__global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(Work W, int round) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ double s_ub[kWavesPerBlock][BcpVisitor<D, F32>::kDensePath ? 2 * D * kWave : 1];
-  const int C = W.desc->n_cells;
-  int cnt[kTreeLevels + 2];
-  level_counts(C, cnt);
-  const int top = top_level(cnt);
-  if (round > top) return;
-  const int w = threadIdx.x / kWave;
-  // Up to W.bcp_split waves share one unit: its points are cut into that many
-  // segments of at least seg_min points, and each wave tests its segment
-  // against every neighbour, so a large cell no longer sets the kernel's length
-  // alone.  Links are made from the same cell, and a segment that finds its
-  // neighbour already joined (by another segment) skips it.
-  const int split = W.bcp_split;
-  const int seg_min = max(kBcpSegment, (int)((long long)kSegMean * W.n / max(C, 1)));
-  Counters tot;
-  const UnitRange R = xcd_units((long long)C * split);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int g = (int)(u / split);
-    const int part = (int)(u % split);
-    const int umax = round < 0 ? 0 : min(round, W.unit_max_level);
-    int ulevel = -1;
-    if (W.coreCount[g] > 0 && (umax == 0 || W.nroot[1][g >> 6] < 0)) ulevel = 0;
-    for (int l = 1; l <= umax && ulevel < 0; ++l) {
-      const int idx = g >> (6 * l);
-      if ((idx << (6 * l)) != g) break;
-      if (W.nroot[l][idx] >= 0 && (l == umax || W.nroot[l + 1][g >> (6 * (l + 1))] < 0)) ulevel = l;
-    }
-    if (ulevel < 0) continue;
-    // Warm start with the previous setting's core counts: a link the union-find lacks
-    // needs a pair within eps with a point that was not core before (pairs of earlier
-    // core points were all linked), so only cells that gained core points act, and
-    // they test every neighbour cell, not only those of lower index.
-    const bool gained_only = WARM && W.prev_core_count != nullptr;
-    if (gained_only && W.coreCount[g] <= W.prev_core_count[g]) continue;
-    BcpVisitor<D, F32> v;
-    v.W = &W;
-    v.F = Flat{s_pref[w], s_start[w]};
-    v.ub = s_ub[w];
-    v.ub_ready = false;
-    v.uq.E2 = W.E2b;  // ClusterCore's radius (eps, or eps (1 + rho) when approximate)
-    v.tin = W.desc->tinb;
-    v.tout = W.desc->toutb;
-    v.one_cell = ulevel == 0;
-    if (ulevel == 0) {
-      v.ps = W.cellStart[g];
-      v.pe = W.cellStart[g + 1];
-      v.hmax = gained_only ? C : g;
-      v.ucell = g;
-      load_box<D>(W.tree, g, v.uq);
-    } else {
-      const int idx = g >> (6 * ulevel);
-      const int first = idx << (6 * ulevel);
-      const int last = min(C, (idx + 1) << (6 * ulevel)) - 1;
-      v.ps = W.cellStart[first];
-      v.pe = W.cellStart[last + 1];
-      v.hmax = first;
-      v.ucell = W.nroot[ulevel][idx];
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        v.uq.lo[d] = W.tree.lo[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
-        v.uq.hi[d] = W.tree.hi[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
+__global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(WS ws, int round) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ double s_ub[kWavesPerBlock][BcpVisitor<D, F32>::kDensePath ? 2 * D * kWave : 1];
+    const int C = W.desc->n_cells;
+    int cnt[kTreeLevels + 2];
+    level_counts(C, cnt);
+    const int top = top_level(cnt);
+    if (round > top) return;
+    const int w = threadIdx.x / kWave;
+    // Up to W.bcp_split waves share one unit: its points are cut into that many
+    // segments of at least seg_min points, and each wave tests its segment
+    // against every neighbour, so a large cell no longer sets the kernel's length
+    // alone.  Links are made from the same cell, and a segment that finds its
+    // neighbour already joined (by another segment) skips it.
+    const int split = W.bcp_split;
+    const int seg_min = max(kBcpSegment, (int)((long long)kSegMean * W.n / max(C, 1)));
+    Counters tot;
+    const UnitRange R = xcd_units((long long)C * split);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int g = (int)(u / split);
+      const int part = (int)(u % split);
+      const int umax = round < 0 ? 0 : min(round, W.unit_max_level);
+      int ulevel = -1;
+      if (W.coreCount[g] > 0 && (umax == 0 || W.nroot[1][g >> 6] < 0)) ulevel = 0;
+      for (int l = 1; l <= umax && ulevel < 0; ++l) {
+        const int idx = g >> (6 * l);
+        if ((idx << (6 * l)) != g) break;
+        if (W.nroot[l][idx] >= 0 && (l == umax || W.nroot[l + 1][g >> (6 * (l + 1))] < 0)) ulevel = l;
       }
+      if (ulevel < 0) continue;
+      // Warm start with the previous setting's core counts: a link the union-find lacks
+      // needs a pair within eps with a point that was not core before (pairs of earlier
+      // core points were all linked), so only cells that gained core points act, and
+      // they test every neighbour cell, not only those of lower index.
+      const bool gained_only = WARM && W.prev_core_count != nullptr;
+      if (gained_only && W.coreCount[g] <= W.prev_core_count[g]) continue;
+      BcpVisitor<D, F32> v;
+      v.W = &W;
+      v.F = Flat{s_pref[w], s_start[w]};
+      v.ub = s_ub[w];
+      v.ub_ready = false;
+      v.uq.E2 = W.E2b;  // ClusterCore's radius (eps, or eps (1 + rho) when approximate)
+      v.tin = W.desc->tinb;
+      v.tout = W.desc->toutb;
+      v.one_cell = ulevel == 0;
+      if (ulevel == 0) {
+        v.ps = W.cellStart[g];
+        v.pe = W.cellStart[g + 1];
+        v.hmax = gained_only ? C : g;
+        v.ucell = g;
+        load_box<D>(W.tree, g, v.uq);
+      } else {
+        const int idx = g >> (6 * ulevel);
+        const int first = idx << (6 * ulevel);
+        const int last = min(C, (idx + 1) << (6 * ulevel)) - 1;
+        v.ps = W.cellStart[first];
+        v.pe = W.cellStart[last + 1];
+        v.hmax = first;
+        v.ucell = W.nroot[ulevel][idx];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          v.uq.lo[d] = W.tree.lo[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
+          v.uq.hi[d] = W.tree.hi[ulevel][(size_t)d * W.tree.cap[ulevel] + idx];
+        }
+      }
+      {
+        const int m = v.pe - v.ps;
+        const int nseg = max(1, min(split, m / seg_min));
+        if (part >= nseg) continue;
+        const int len = (m + nseg - 1) / nseg;
+        v.ps += part * len;
+        v.pe = min(v.pe, v.ps + len);
+      }
+      v.c0 = v.ps >> 6;
+      v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
+      // a warm start prunes by the node roots taken before the launch from the start:
+      // the cell's parent is its root after most links (a full find here made the
+      // compiler spill the kernel's registers; the walk's groups refresh the root)
+      v.rg = WARM ? W.parent[v.ucell] : v.ucell;
+      v.excl_level = round >= 1 ? round : -1;
+      v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
+      // (a warm start with known previous counts takes no node roots: see stage_cluster)
+      v.prune = (WARM && !gained_only) || round >= 1;
+      const int anc_level = round < 0 ? top + 1 : round + 1;
+      const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
+      if (round < 0 && ulevel == 0)
+        walk_from_list<D>(W, C, g, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
+      else
+        walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
+      tot.add(v.ctr);
     }
-    {
-      const int m = v.pe - v.ps;
-      const int nseg = max(1, min(split, m / seg_min));
-      if (part >= nseg) continue;
-      const int len = (m + nseg - 1) / nseg;
-      v.ps += part * len;
-      v.pe = min(v.pe, v.ps + len);
-    }
-    v.c0 = v.ps >> 6;
-    v.nchk = ((v.pe - 1) >> 6) - v.c0 + 1;
-    // a warm start prunes by the node roots taken before the launch from the start:
-    // the cell's parent is its root after most links (a full find here made the
-    // compiler spill the kernel's registers; the walk's groups refresh the root)
-    v.rg = WARM ? W.parent[v.ucell] : v.ucell;
-    v.excl_level = round >= 1 ? round : -1;
-    v.excl_idx = round >= 1 ? (g >> (6 * round)) : 0;
-    // (a warm start with known previous counts takes no node roots: see stage_cluster)
-    v.prune = (WARM && !gained_only) || round >= 1;
-    const int anc_level = round < 0 ? top + 1 : round + 1;
-    const int anc = (round < 0 || round == top) ? 0 : (g >> (6 * anc_level));
-    if (round < 0 && ulevel == 0)
-      walk_from_list<D>(W, C, g, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
-    else
-      walk_subtree<D>(W.tree, C, anc_level, anc, v.uq, v, WalkStack{s_m[w], s_cb[w], nullptr});
-    tot.add(v.ctr);
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 // Node roots for pruning: per node, the common root of its core cells, -1 when
 // they are in several components, kNodeNoCore when it has no core cell.
-__global__ __launch_bounds__(kBlock) void k_node_roots(Work W, int level) {
-  const int C = W.desc->n_cells;
-  int cnt[kTreeLevels + 2];
-  level_counts(C, cnt);
-  const int lane = lane_id();
-  for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < cnt[level];
-       j += gridDim.x * kWavesPerBlock) {
-    const int ch = j * 64 + lane;
-    int v = kNodeNoCore;
-    if (ch < cnt[level - 1]) {
-      if (level == 1) v = W.coreCount[ch] > 0 ? uf_find(W.parent, ch) : kNodeNoCore;
-      else v = W.nroot[level - 1][ch];
+template <class WS>
+__global__ __launch_bounds__(kBlock) void k_node_roots(WS ws, int level) {
+  ws.each_wave([&](const Work& W) {
+    const int C = W.desc->n_cells;
+    int cnt[kTreeLevels + 2];
+    level_counts(C, cnt);
+    const int lane = lane_id();
+    for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < cnt[level];
+         j += gridDim.x * kWavesPerBlock) {
+      const int ch = j * 64 + lane;
+      int v = kNodeNoCore;
+      if (ch < cnt[level - 1]) {
+        if (level == 1) v = W.coreCount[ch] > 0 ? uf_find(W.parent, ch) : kNodeNoCore;
+        else v = W.nroot[level - 1][ch];
+      }
+      const bool mixed = ballot(v == -1) != 0;
+      const int hi = wave_max(v);
+      const int lo = wave_min(v == kNodeNoCore ? kIntMax : v);
+      int r;
+      if (mixed) r = -1;
+      else if (hi == kNodeNoCore) r = kNodeNoCore;
+      else r = (lo == hi) ? hi : -1;
+      if (lane == 0) W.nroot[level][j] = r;
     }
-    const bool mixed = ballot(v == -1) != 0;
-    const int hi = wave_max(v);
-    const int lo = wave_min(v == kNodeNoCore ? kIntMax : v);
-    int r;
-    if (mixed) r = -1;
-    else if (hi == kNodeNoCore) r = kNodeNoCore;
-    else r = (lo == hi) ? hi : -1;
-    if (lane == 0) W.nroot[level][j] = r;
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1442,35 +1466,41 @@ __global__ __launch_bounds__(kBlock) void k_node_roots(Work W, int level) {
 // the component.  Each wave takes 64 cells, reduces the minimum per distinct root
 // among them and issues one atomicMin per root.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_relabel_min(Work W) {
-  const int C = W.desc->n_cells;
-  const int lane = lane_id();
-  const int nchunks = (C + kWave - 1) / kWave;
-  for (int ch = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; ch < nchunks;
-       ch += gridDim.x * kWavesPerBlock) {
-    const int c = ch * kWave + lane;
-    int root = -1, mn = kIntMax;
-    if (c < C && W.coreCount[c] > 0) {
-      root = uf_find(W.parent, c);
-      mn = W.cellMin[c];
+template <class WS>
+__global__ __launch_bounds__(kBlock) void k_relabel_min(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    const int C = W.desc->n_cells;
+    const int lane = lane_id();
+    const int nchunks = (C + kWave - 1) / kWave;
+    for (int ch = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; ch < nchunks;
+         ch += gridDim.x * kWavesPerBlock) {
+      const int c = ch * kWave + lane;
+      int root = -1, mn = kIntMax;
+      if (c < C && W.coreCount[c] > 0) {
+        root = uf_find(W.parent, c);
+        mn = W.cellMin[c];
+      }
+      uint64_t todo = ballot(root >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int r = __shfl(root, leader, kWave);
+        const bool mine = root == r;
+        const int v = wave_min(mine ? mn : kIntMax);
+        if (lane == leader) atomicMin(&W.minIdx[r], v);
+        todo &= ~ballot(mine);
+      }
     }
-    uint64_t todo = ballot(root >= 0);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int r = __shfl(root, leader, kWave);
-      const bool mine = root == r;
-      const int v = wave_min(mine ? mn : kIntMax);
-      if (lane == leader) atomicMin(&W.minIdx[r], v);
-      todo &= ~ballot(mine);
-    }
-  }
+  });
 }
 
-__global__ void k_cell_label(Work W) {
-  const int C = W.desc->n_cells;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-    W.cellLabel[c] = W.coreCount[c] > 0 ? W.minIdx[uf_find(W.parent, c)] : -1;
-  }
+template <class WS>
+__global__ void k_cell_label(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    const int C = W.desc->n_cells;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+      W.cellLabel[c] = W.coreCount[c] > 0 ? W.minIdx[uf_find(W.parent, c)] : -1;
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1557,87 +1587,99 @@ struct BorderVisitor {
   }
 };
 
-template <int D, bool F32>
-__global__ __launch_bounds__(kBlock) void k_border(Work W) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_pos[kWavesPerBlock][kWave];
-  const int C = W.desc->n_cells;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int n = W.n;
-  Counters tot;
-  const UnitRange R = xcd_units(C);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int g = (int)u;
-    const int s = W.cellStart[g], e = W.cellStart[g + 1];
-    if (W.coreCount[g] == e - s) continue;
-    Query<D> q;
-    q.E2 = W.E2;
-    load_box<D>(W.tree, g, q);
-    const int own = W.coreCount[g] > 0 ? W.cellLabel[g] : kIntMax;
-    int i = s;
-    while (i < e) {
-      // compact the next (up to 64) non-core positions of g into s_pos
-      int taken = 0;
-      while (i < e && taken < kWave) {
-        const int k = i + lane;
-        const bool nc = k < e && (W.coreS[k] & W.core_mask) == 0;
-        const uint64_t bm = ballot(nc);
-        const int rank = __popcll(bm & lanemask_lt());
-        const int cnt = __popcll(bm);
-        const int room = kWave - taken;
-        if (nc && rank < room) s_pos[w][taken + rank] = k;
-        if (cnt <= room) {
-          taken += cnt;
-          i += kWave;
-        } else {
-          const uint64_t lastm = ballot(nc && rank == room - 1);
-          i += __ffsll((long long)lastm);  // one past the last lane taken
-          taken = kWave;
+template <int D, bool F32, class WS>
+__global__ __launch_bounds__(kBlock) void k_border(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_pos[kWavesPerBlock][kWave];
+    const int C = W.desc->n_cells;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int n = W.n;
+    Counters tot;
+    const UnitRange R = xcd_units(C);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int g = (int)u;
+      const int s = W.cellStart[g], e = W.cellStart[g + 1];
+      if (W.coreCount[g] == e - s) continue;
+      Query<D> q;
+      q.E2 = W.E2;
+      load_box<D>(W.tree, g, q);
+      const int own = W.coreCount[g] > 0 ? W.cellLabel[g] : kIntMax;
+      int i = s;
+      while (i < e) {
+        // compact the next (up to 64) non-core positions of g that have neighbours
+        // outside g into s_pos.  A non-core point's count is exact (below every cap)
+        // and includes the |g| points of its own cell, all within eps of it; a count
+        // of |g| means no neighbour elsewhere, so its label is g's cluster or noise.
+        int taken = 0;
+        while (i < e && taken < kWave) {
+          const int k = i + lane;
+          bool nc = k < e && (W.coreS[k] & W.core_mask) == 0;
+          if (nc && W.cnt[k] == e - s) {
+            W.blabel[k] = own == kIntMax ? -1 : own;
+            nc = false;
+          }
+          const uint64_t bm = ballot(nc);
+          const int rank = __popcll(bm & lanemask_lt());
+          const int cnt = __popcll(bm);
+          const int room = kWave - taken;
+          if (nc && rank < room) s_pos[w][taken + rank] = k;
+          if (cnt <= room) {
+            taken += cnt;
+            i += kWave;
+          } else {
+            const uint64_t lastm = ballot(nc && rank == room - 1);
+            i += __ffsll((long long)lastm);  // one past the last lane taken
+            taken = kWave;
+          }
         }
-      }
-      wave_sync();
-      const int pos = lane < taken ? s_pos[w][lane] : -1;
-      wave_sync();
-      if (taken == 0) break;
-      BorderVisitor<D, F32> v;
-      v.W = &W;
-      v.F = Flat{s_pref[w], s_start[w]};
-      v.g = g;
-      v.pm = taken;
-      v.best = own;
-      v.pidx = pos;
-      v.tin = W.desc->tin;
-      v.tout = W.desc->tout;
+        wave_sync();
+        const int pos = lane < taken ? s_pos[w][lane] : -1;
+        wave_sync();
+        if (taken == 0) break;
+        BorderVisitor<D, F32> v;
+        v.W = &W;
+        v.F = Flat{s_pref[w], s_start[w]};
+        v.g = g;
+        v.pm = taken;
+        v.best = own;
+        v.pidx = pos;
+        v.tin = W.desc->tin;
+        v.tout = W.desc->tout;
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        v.p[d] = 0.0;
-        v.ap[d] = 0.0f;
+        for (int d = 0; d < D; ++d) {
+          v.p[d] = 0.0;
+          v.ap[d] = 0.0f;
+        }
+        if (lane < taken) {
+          if constexpr (F32) load_local<D>(W.X32, n, pos, v.ap);
+          else load_point<D>(W.X, n, pos, v.p);
+        }
+        if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
+        walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
+        if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
+        tot.add(v.ctr);
       }
-      if (lane < taken) {
-        if constexpr (F32) load_local<D>(W.X32, n, pos, v.ap);
-        else load_point<D>(W.X, n, pos, v.p);
-      }
-      if constexpr (F32) load_anchor<D>(W.tree, g, v.ag);
-      walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], nullptr});
-      if (lane < taken) W.blabel[pos] = v.best == kIntMax ? -1 : v.best;
-      tot.add(v.ctr);
     }
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 // Results back to input order.
-__global__ void k_scatter(Work W) {
-  const int n = W.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int src = W.perm[i];
-    const uint8_t c = (W.coreS[i] & W.core_mask) ? 1 : 0;
-    W.core_out[src] = c;
-    W.label_out[src] = c ? W.cellLabel[W.cellOf[i]] : W.blabel[i];
-  }
+template <class WS>
+__global__ void k_scatter(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    const int n = W.n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+      const int src = W.perm[i];
+      const uint8_t c = (W.coreS[i] & W.core_mask) ? 1 : 0;
+      W.core_out[src] = c;
+      W.label_out[src] = c ? W.cellLabel[W.cellOf[i]] : W.blabel[i];
+    }
+  });
 }
 
 }  // namespace db

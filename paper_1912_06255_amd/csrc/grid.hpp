@@ -81,6 +81,7 @@ struct Work {
   int sparse_mode;    // 0: per-cell kernels, 1: batched sparse kernels
   uint32_t core_mask; // bit of this setting in coreS (settings of one eps share one byte per point)
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
+  double eps;
   double E2;
   double E2b;         // ClusterCore's pair test: E2, or fl(R^2), R = fl(eps fl(1 + rho)), for approximate DBSCAN
   double side;
@@ -128,6 +129,49 @@ struct Work {
   int32_t* cnt;       // [n] neighbours within eps, capped at count_cap, cell order
 };
 
+// What a kernel runs on: one grid (OneWork, the Work passed by value) or a group of
+// grids (ManyWork: a table of Works in device memory).  A group shares each launch:
+// every workgroup takes its share of each grid in turn, so small grids fill the
+// chip together instead of one launch each.  Kernels size their launch for the
+// largest grid of a group; the parts of a launch a smaller grid does not need find
+// no work (or no tile) in it.
+// each(): for kernels that share memory between the waves of a workgroup (a barrier
+// separates the grids); each_wave(): for kernels whose waves work alone (shared
+// memory per wave, no barrier), so that a wave goes on to the next grid as soon as
+// its own share of this one is done.
+struct OneWork {
+  Work W;
+  template <class F>
+  DB_DEV void each(F&& f) const {
+    f(W);
+  }
+  template <class F>
+  DB_DEV void each_wave(F&& f) const {
+    f(W);
+  }
+};
+
+// The table is read through the constant address space: it is not written while a
+// kernel runs, and the compiler then loads each grid's fields into scalar registers,
+// as it does for a Work passed by value.
+using ConstWork = const __attribute__((address_space(4))) Work;
+
+struct ManyWork {
+  ConstWork* Ws;
+  int k;
+  template <class F>
+  DB_DEV void each(F&& f) const {
+    for (int c = 0; c < k; ++c) {
+      if (c) __syncthreads();  // the previous grid's use of shared memory is over
+      f(*(const Work*)&Ws[c]);
+    }
+  }
+  template <class F>
+  DB_DEV void each_wave(F&& f) const {
+    for (int c = 0; c < k; ++c) f(*(const Work*)&Ws[c]);
+  }
+};
+
 constexpr int kBBoxBlocks = 512;
 
 DB_DEV uint32_t epoch_of(const GridDesc* desc, uint32_t slot) {
@@ -161,51 +205,53 @@ DB_DEV void init_call(const Work& W, int first) {
 // ---------------------------------------------------------------------------
 // Bounding box (partials per block, then one block finalises the grid).
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_bbox_partial(Work W, int first) {
-  __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
-  __shared__ int s_bad;
-  if (blockIdx.x == 0) init_call(W, first);  // nothing below reads what it resets
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  double lo[D], hi[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    lo[k] = __builtin_inf();
-    hi[k] = -__builtin_inf();
-  }
-  bool bad = false;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(WS ws, int first) {
+  ws.each([&](const Work& W) {
+    __shared__ double s_lo[kWavesPerBlock][D], s_hi[kWavesPerBlock][D];
+    __shared__ int s_bad;
+    if (blockIdx.x == 0) init_call(W, first);  // nothing below reads what it resets
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    double lo[D], hi[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double v = W.pts[(size_t)i * D + k];
-      bad |= !__builtin_isfinite(v);
-      lo[k] = fmin(lo[k], v);
-      hi[k] = fmax(hi[k], v);
+      lo[k] = __builtin_inf();
+      hi[k] = -__builtin_inf();
     }
-  }
-  if (ballot(bad) && lane_id() == 0) s_bad = 1;
-  const int w = threadIdx.x / kWave;
+    bool bad = false;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const double a = wave_min(lo[k]), b = wave_max(hi[k]);
-    if (lane_id() == 0) {
-      s_lo[w][k] = a;
-      s_hi[w][k] = b;
+      for (int k = 0; k < D; ++k) {
+        const double v = W.pts[(size_t)i * D + k];
+        bad |= !__builtin_isfinite(v);
+        lo[k] = fmin(lo[k], v);
+        hi[k] = fmax(hi[k], v);
+      }
     }
-  }
-  __syncthreads();
-  if (threadIdx.x < D) {
-    const int k = threadIdx.x;
-    double a = s_lo[0][k], b = s_hi[0][k];
-    for (int j = 1; j < kWavesPerBlock; ++j) {
-      a = fmin(a, s_lo[j][k]);
-      b = fmax(b, s_hi[j][k]);
+    if (ballot(bad) && lane_id() == 0) s_bad = 1;
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double a = wave_min(lo[k]), b = wave_max(hi[k]);
+      if (lane_id() == 0) {
+        s_lo[w][k] = a;
+        s_hi[w][k] = b;
+      }
     }
-    W.bbox_part[blockIdx.x * 2 * kMaxD + k] = a;
-    W.bbox_part[blockIdx.x * 2 * kMaxD + kMaxD + k] = b;
-  }
-  if (threadIdx.x == 0) W.bbox_flag[blockIdx.x] = (uint32_t)s_bad;
+    __syncthreads();
+    if (threadIdx.x < D) {
+      const int k = threadIdx.x;
+      double a = s_lo[0][k], b = s_hi[0][k];
+      for (int j = 1; j < kWavesPerBlock; ++j) {
+        a = fmin(a, s_lo[j][k]);
+        b = fmax(b, s_hi[j][k]);
+      }
+      W.bbox_part[blockIdx.x * 2 * kMaxD + k] = a;
+      W.bbox_part[blockIdx.x * 2 * kMaxD + kMaxD + k] = b;
+    }
+    if (threadIdx.x == 0) W.bbox_flag[blockIdx.x] = (uint32_t)s_bad;
+  });
 }
 
 // Grid: origin o = min corner, q_k = floor((x_k - o_k) / s).  The Morton key holds
@@ -335,50 +381,62 @@ DB_DEV uint64_t morton_key(const double* x, const KeyGrid& g, const int (&bits)[
   return key;
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_keys(Work W, int nparts) {
-  __shared__ uint32_t s_hist[8][256];
-  __shared__ KeyGrid g;
-  for (int i = threadIdx.x; i < 8 * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
-  grid_from_partials<D>(W, nparts, g);  // ends with a barrier
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    GridDesc* d = W.desc;
-    for (int k = 0; k < kMaxD; ++k) {
-      d->origin[k] = k < D ? g.origin[k] : 0.0;
-      d->bits[k] = g.bits[k];
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_keys(WS ws, int nparts) {
+  ws.each([&](const Work& W) {
+    __shared__ uint32_t s_hist[8][256];
+    __shared__ KeyGrid g;
+    for (int i = threadIdx.x; i < 8 * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
+    // The look-back words of this grid's scans start cleared.  The region can hold
+    // anything an earlier call left there (another grid's keys, for instance), and
+    // a stale word whose high bits happen to equal a tag of this call would be read
+    // as a predecessor's prefix, leaving the permutation with holes.
+    {
+      const size_t nlb = (size_t)((W.n + kTile - 1) / kTile) * 256;
+      for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < nlb;
+           i += (size_t)gridDim.x * kBlock)
+        W.lbstate[i] = 0;
     }
-    d->side = g.side;
-    d->shift = g.shift;
-    d->fine_bits = g.fine;
-    d->cell_key_shift = g.fine * D;
-    d->total_bits = g.total;
-    d->passes = g.passes;
-    if (g.bad) d->status |= 1u;
-  }
-  int bits[D];
-  int maxb = 0;
+    grid_from_partials<D>(W, nparts, g);  // ends with a barrier
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      GridDesc* d = W.desc;
+      for (int k = 0; k < kMaxD; ++k) {
+        d->origin[k] = k < D ? g.origin[k] : 0.0;
+        d->bits[k] = g.bits[k];
+      }
+      d->side = g.side;
+      d->shift = g.shift;
+      d->fine_bits = g.fine;
+      d->cell_key_shift = g.fine * D;
+      d->total_bits = g.total;
+      d->passes = g.passes;
+      if (g.bad) d->status |= 1u;
+    }
+    int bits[D];
+    int maxb = 0;
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    bits[k] = g.bits[k];
-    maxb = max(maxb, bits[k]);
-  }
-  const int passes = g.passes;
-  const int fine = g.fine;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
-    double x[D];
+    for (int k = 0; k < D; ++k) {
+      bits[k] = g.bits[k];
+      maxb = max(maxb, bits[k]);
+    }
+    const int passes = g.passes;
+    const int fine = g.fine;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < W.n; i += gridDim.x * kBlock) {
+      double x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = W.pts[(size_t)i * D + k];
-    const uint64_t key = morton_key<D>(x, g, bits, maxb, fine);
-    W.keyA[i] = key;
-    W.idxA[i] = (uint32_t)i;
-    W.cnt[i] = 0;  // MarkCore's waves add their shares to it
-    for (int p = 0; p < passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < passes * 256; i += kBlock) {
-    const uint32_t v = (&s_hist[0][0])[i];
-    if (v) atomicAdd(&W.ghist[i], v);
-  }
+      for (int k = 0; k < D; ++k) x[k] = W.pts[(size_t)i * D + k];
+      const uint64_t key = morton_key<D>(x, g, bits, maxb, fine);
+      W.keyA[i] = key;
+      W.idxA[i] = (uint32_t)i;
+      W.cnt[i] = 0;  // MarkCore's waves add their shares to it
+      for (int p = 0; p < passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * 256; i += kBlock) {
+      const uint32_t v = (&s_hist[0][0])[i];
+      if (v) atomicAdd(&W.ghist[i], v);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -397,93 +455,98 @@ DB_DEV uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_tmp /*[kWavesPerBloc
   return off + (uint32_t)incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort_pass(Work W, int pass, int ntiles) {
-  __shared__ uint32_t s_wcnt[kWavesPerBlock][256];
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_tmp[kWavesPerBlock];
-  __shared__ int s_tile;
-  const GridDesc* g = W.desc;
-  if (pass >= g->passes) return;
-  const uint64_t* kin = (pass & 1) ? W.keyB : W.keyA;
-  const uint32_t* vin = (pass & 1) ? W.idxB : W.idxA;
-  uint64_t* kout = (pass & 1) ? W.keyA : W.keyB;
-  uint32_t* vout = (pass & 1) ? W.idxA : W.idxB;
-  const uint32_t epoch = epoch_of(g, pass);
-  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  if (tid == 0) s_tile = atomicAdd(&W.tilectr[pass], 1);
-  for (int i = tid; i < kWavesPerBlock * 256; i += kBlock) (&s_wcnt[0][0])[i] = 0;
-  __syncthreads();
-  const int tile = s_tile;
-  const int shift = 8 * pass;
-  const int n = W.n;
+template <class WS>
+__global__ __launch_bounds__(kBlock) void k_sort_pass(WS ws, int pass) {
+  ws.each([&](const Work& W) {
+    __shared__ uint32_t s_wcnt[kWavesPerBlock][256];
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_tmp[kWavesPerBlock];
+    __shared__ int s_tile;
+    const GridDesc* g = W.desc;
+    if (pass >= g->passes) return;
+    const uint64_t* kin = (pass & 1) ? W.keyB : W.keyA;
+    const uint32_t* vin = (pass & 1) ? W.idxB : W.idxA;
+    uint64_t* kout = (pass & 1) ? W.keyA : W.keyB;
+    uint32_t* vout = (pass & 1) ? W.idxA : W.idxB;
+    const uint32_t epoch = epoch_of(g, pass);
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    if (tid == 0) s_tile = atomicAdd(&W.tilectr[pass], 1);
+    for (int i = tid; i < kWavesPerBlock * 256; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int tile = s_tile;
+    // (a launch shared by several grids has as many workgroups as the largest needs)
+    if (tile >= (W.n + kTile - 1) / kTile) return;
+    const int shift = 8 * pass;
+    const int n = W.n;
 
-  uint64_t key[kSortItems];
-  uint32_t val[kSortItems];
-  uint32_t rnk[kSortItems];
-  const int base_idx = tile * kTile + w * (kWave * kSortItems);
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rnk[kSortItems];
+    const int base_idx = tile * kTile + w * (kWave * kSortItems);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int idx = base_idx + j * kWave + lane;
-    const bool valid = idx < n;
-    key[j] = valid ? kin[idx] : 0ull;
-    val[j] = valid ? vin[idx] : 0u;
-  }
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int idx = base_idx + j * kWave + lane;
-    const bool valid = idx < n;
-    const uint32_t digit = (uint32_t)(key[j] >> shift) & 255u;
-    uint64_t peers = ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (digit >> b) & 1u;
-      const uint64_t bb = ballot(bit);
-      peers &= bit ? bb : ~bb;
+    for (int j = 0; j < kSortItems; ++j) {
+      const int idx = base_idx + j * kWave + lane;
+      const bool valid = idx < n;
+      key[j] = valid ? kin[idx] : 0ull;
+      val[j] = valid ? vin[idx] : 0u;
     }
-    const uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    const uint32_t old = valid ? s_wcnt[w][digit] : 0u;
-    wave_sync();
-    if (valid && before == 0) s_wcnt[w][digit] = old + cnt;
-    wave_sync();
-    rnk[j] = old + before;
-  }
-  __syncthreads();
-  // per digit: offsets of each wave inside the tile, tile total, look-back.
-  {
-    const int dg = tid;
-    uint32_t run = 0;
 #pragma unroll
-    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
-      const uint32_t t = s_wcnt[w2][dg];
-      s_wcnt[w2][dg] = run;
-      run += t;
-    }
-    uint64_t* st = W.lbstate + (size_t)tile * 256 + dg;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      st_rel(st, lb_word(epoch, kFlagIncl, run));
-    } else {
-      st_rel(st, lb_word(epoch, kFlagAgg, run));
-      excl = lookback_exclusive(W.lbstate + dg, 256, tile, epoch, &W.desc->status);
-      st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
-    }
-    const uint32_t gstart = block_excl_scan_256(W.ghist[pass * 256 + dg], s_tmp);
-    s_base[dg] = gstart + excl;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int idx = base_idx + j * kWave + lane;
-    if (idx < n) {
+    for (int j = 0; j < kSortItems; ++j) {
+      const int idx = base_idx + j * kWave + lane;
+      const bool valid = idx < n;
       const uint32_t digit = (uint32_t)(key[j] >> shift) & 255u;
-      const uint32_t dst = s_base[digit] + s_wcnt[w][digit] + rnk[j];
-      if (dst < (uint32_t)n) {  // always true unless a look-back wait expired
-        kout[dst] = key[j];
-        vout[dst] = val[j];
+      uint64_t peers = ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (digit >> b) & 1u;
+        const uint64_t bb = ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      const uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
+      const uint32_t cnt = (uint32_t)__popcll(peers);
+      const uint32_t old = valid ? s_wcnt[w][digit] : 0u;
+      wave_sync();
+      if (valid && before == 0) s_wcnt[w][digit] = old + cnt;
+      wave_sync();
+      rnk[j] = old + before;
+    }
+    __syncthreads();
+    // per digit: offsets of each wave inside the tile, tile total, look-back.
+    {
+      const int dg = tid;
+      uint32_t run = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+        const uint32_t t = s_wcnt[w2][dg];
+        s_wcnt[w2][dg] = run;
+        run += t;
+      }
+      uint64_t* st = W.lbstate + (size_t)tile * 256 + dg;
+      uint32_t excl = 0;
+      if (tile == 0) {
+        st_rel(st, lb_word(epoch, kFlagIncl, run));
+      } else {
+        st_rel(st, lb_word(epoch, kFlagAgg, run));
+        excl = lookback_exclusive(W.lbstate + dg, 256, tile, epoch, &W.desc->status);
+        st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
+      }
+      const uint32_t gstart = block_excl_scan_256(W.ghist[pass * 256 + dg], s_tmp);
+      s_base[dg] = gstart + excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int idx = base_idx + j * kWave + lane;
+      if (idx < n) {
+        const uint32_t digit = (uint32_t)(key[j] >> shift) & 255u;
+        const uint32_t dst = s_base[digit] + s_wcnt[w][digit] + rnk[j];
+        if (dst < (uint32_t)n) {  // always true unless a look-back wait expired
+          kout[dst] = key[j];
+          vout[dst] = val[j];
+        }
       }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -494,93 +557,96 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(Work W, int pass, int ntil
 // derived from a finer one (k_derive): the points keep their order and the cells
 // are the runs of equal kept keys (skey >> cell_key_shift).
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_cells(Work W, int mode) {
-  __shared__ uint32_t s_tmp[kWavesPerBlock];
-  __shared__ uint32_t s_excl;
-  __shared__ uint32_t s_tot;
-  __shared__ int s_tile;
-  const GridDesc* g = W.desc;
-  if (mode == 1 && g->n_unsafe == 0) return;
-  const int n = W.n;
-  const bool odd = (g->passes & 1) != 0;
-  const uint64_t* keys = odd ? W.keyB : W.keyA;
-  const uint32_t* idx = odd ? W.idxB : W.idxA;
-  // (mode 1 writes the second set of cell arrays; modes 0 and 2 the first)
-  int32_t* cof = mode == 1 ? W.cellOf2 : W.cellOf;
-  int32_t* cst = mode == 1 ? W.cellStart2 : W.cellStart;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_tile = atomicAdd(&W.tilectr[8 + mode], 1);
-  __syncthreads();
-  const int tile = s_tile;
-  const uint32_t epoch = epoch_of(g, 8 + mode);
-  const int cks = g->cell_key_shift;
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_cells(WS ws, int mode) {
+  ws.each([&](const Work& W) {
+    __shared__ uint32_t s_tmp[kWavesPerBlock];
+    __shared__ uint32_t s_excl;
+    __shared__ uint32_t s_tot;
+    __shared__ int s_tile;
+    const GridDesc* g = W.desc;
+    if (mode == 1 && g->n_unsafe == 0) return;
+    const int n = W.n;
+    const bool odd = (g->passes & 1) != 0;
+    const uint64_t* keys = odd ? W.keyB : W.keyA;
+    const uint32_t* idx = odd ? W.idxB : W.idxA;
+    // (mode 1 writes the second set of cell arrays; modes 0 and 2 the first)
+    int32_t* cof = mode == 1 ? W.cellOf2 : W.cellOf;
+    int32_t* cst = mode == 1 ? W.cellStart2 : W.cellStart;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_tile = atomicAdd(&W.tilectr[8 + mode], 1);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= (n + kTile - 1) / kTile) return;  // (see k_sort_pass)
+    const uint32_t epoch = epoch_of(g, 8 + mode);
+    const int cks = g->cell_key_shift;
 
-  bool head[kSortItems];
-  uint32_t pre[kSortItems];
-  uint32_t run = 0;
+    bool head[kSortItems];
+    uint32_t pre[kSortItems];
+    uint32_t run = 0;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int i = tile * kTile + j * kBlock + tid;
-    bool h = false;
-    if (i < n) {
-      if (i == 0) {
-        h = true;
-      } else if (mode == 0) {
-        h = (keys[i] >> cks) != (keys[i - 1] >> cks);
-      } else if (mode == 2) {
-        h = (W.skey[i] >> cks) != (W.skey[i - 1] >> cks);
+    for (int j = 0; j < kSortItems; ++j) {
+      const int i = tile * kTile + j * kBlock + tid;
+      bool h = false;
+      if (i < n) {
+        if (i == 0) {
+          h = true;
+        } else if (mode == 0) {
+          h = (keys[i] >> cks) != (keys[i - 1] >> cks);
+        } else if (mode == 2) {
+          h = (W.skey[i] >> cks) != (W.skey[i - 1] >> cks);
+        } else {
+          const int c = W.cellOf[i];
+          h = c != W.cellOf[i - 1] || W.unsafe[c];
+        }
+      }
+      head[j] = h;
+      const uint32_t ex = block_excl_scan_256(h ? 1u : 0u, s_tmp);
+      pre[j] = run + ex;
+      // block total for this j: last thread's exclusive + its flag
+      if (tid == kBlock - 1) s_tot = ex + (h ? 1u : 0u);
+      __syncthreads();
+      run += s_tot;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      uint64_t* st = W.lbstate + (size_t)tile * 256;
+      uint32_t excl = 0;
+      if (tile == 0) {
+        st_rel(st, lb_word(epoch, kFlagIncl, run));
       } else {
-        const int c = W.cellOf[i];
-        h = c != W.cellOf[i - 1] || W.unsafe[c];
+        st_rel(st, lb_word(epoch, kFlagAgg, run));
+        excl = lookback_exclusive(W.lbstate, 256, tile, epoch, &W.desc->status);
+        st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
+      }
+      s_excl = excl;
+    }
+    __syncthreads();
+    const uint32_t texcl = s_excl;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int i = tile * kTile + j * kBlock + tid;
+      if (i >= n) continue;
+      int cid = (int)(texcl + pre[j] + (head[j] ? 1u : 0u)) - 1;
+      cid = cid < 0 ? 0 : (cid >= n ? n - 1 : cid);  // clamps only after an expired wait
+      cof[i] = cid;
+      if (head[j]) cst[cid] = i;
+      if (i == n - 1) {
+        cst[cid + 1] = n;
+        W.desc->n_cells = cid + 1;
+      }
+      if (mode == 2) W.cnt[i] = 0;  // MarkCore's waves add their shares to it (k_keys did not run)
+      if (mode == 0) {
+        uint32_t src = idx[i];
+        if (src >= (uint32_t)n) src = 0;  // only after an expired wait
+        W.perm[i] = (int32_t)src;
+        if (W.inv) W.inv[src] = i;
+        if (W.skey) W.skey[i] = keys[i];
+#pragma unroll
+        for (int k = 0; k < D; ++k) W.X[(size_t)k * n + i] = W.pts[(size_t)src * D + k];
       }
     }
-    head[j] = h;
-    const uint32_t ex = block_excl_scan_256(h ? 1u : 0u, s_tmp);
-    pre[j] = run + ex;
-    // block total for this j: last thread's exclusive + its flag
-    if (tid == kBlock - 1) s_tot = ex + (h ? 1u : 0u);
-    __syncthreads();
-    run += s_tot;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    uint64_t* st = W.lbstate + (size_t)tile * 256;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      st_rel(st, lb_word(epoch, kFlagIncl, run));
-    } else {
-      st_rel(st, lb_word(epoch, kFlagAgg, run));
-      excl = lookback_exclusive(W.lbstate, 256, tile, epoch, &W.desc->status);
-      st_rel(st, lb_word(epoch, kFlagIncl, excl + run));
-    }
-    s_excl = excl;
-  }
-  __syncthreads();
-  const uint32_t texcl = s_excl;
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int i = tile * kTile + j * kBlock + tid;
-    if (i >= n) continue;
-    int cid = (int)(texcl + pre[j] + (head[j] ? 1u : 0u)) - 1;
-    cid = cid < 0 ? 0 : (cid >= n ? n - 1 : cid);  // clamps only after an expired wait
-    cof[i] = cid;
-    if (head[j]) cst[cid] = i;
-    if (i == n - 1) {
-      cst[cid + 1] = n;
-      W.desc->n_cells = cid + 1;
-    }
-    if (mode == 2) W.cnt[i] = 0;  // MarkCore's waves add their shares to it (k_keys did not run)
-    if (mode == 0) {
-      uint32_t src = idx[i];
-      if (src >= (uint32_t)n) src = 0;  // only after an expired wait
-      W.perm[i] = (int32_t)src;
-      if (W.inv) W.inv[src] = i;
-      if (W.skey) W.skey[i] = keys[i];
-#pragma unroll
-      for (int k = 0; k < D; ++k) W.X[(size_t)k * n + i] = W.pts[(size_t)src * D + k];
-    }
-  }
+  });
 }
 
 // A grid for eps' = 2^j eps from the grid of eps of the same cloud (call
@@ -614,107 +680,109 @@ __global__ __launch_bounds__(kBlock) void k_derive(Work W, int j) {
 // Per-cell float64 point boxes (and the boxes of the aligned 64-point chunks).
 // Every cell's box is written exactly once, without atomics.
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_cell_box(Work W, int only_if_split) {
-  const GridDesc* g = W.desc;
-  if (only_if_split && g->n_unsafe == 0) return;
-  const int n = W.n;
-  const int C = g->n_cells;
-  double* lo = const_cast<double*>(W.tree.lo[0]);
-  double* hi = const_cast<double*>(W.tree.hi[0]);
-  const int lane = lane_id();
-  const int wid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  // after a split the new cells are read from the second arrays, which are also
-  // copied over the first ones here
-  const int32_t* cellOf = only_if_split ? W.cellOf2 : W.cellOf;
-  const int32_t* cellStart = only_if_split ? W.cellStart2 : W.cellStart;
-  if (only_if_split) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
-      if (i < n) W.cellOf[i] = W.cellOf2[i];
-      if (i <= C) W.cellStart[i] = W.cellStart2[i];
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
+  ws.each_wave([&](const Work& W) {
+    const GridDesc* g = W.desc;
+    if (only_if_split && g->n_unsafe == 0) return;
+    const int n = W.n;
+    const int C = g->n_cells;
+    double* lo = const_cast<double*>(W.tree.lo[0]);
+    double* hi = const_cast<double*>(W.tree.hi[0]);
+    const int lane = lane_id();
+    const int wid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    // after a split the new cells are read from the second arrays, which are also
+    // copied over the first ones here
+    const int32_t* cellOf = only_if_split ? W.cellOf2 : W.cellOf;
+    const int32_t* cellStart = only_if_split ? W.cellStart2 : W.cellStart;
+    if (only_if_split) {
+      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+        if (i < n) W.cellOf[i] = W.cellOf2[i];
+        if (i <= C) W.cellStart[i] = W.cellStart2[i];
+      }
     }
-  }
-  const int nw = gridDim.x * kWavesPerBlock;
-  const int nchunks = (n + kWave - 1) / kWave;
-  // (1) Per aligned 64-point chunk: boxes of the cells lying wholly inside it
-  // (segmented wave reduction) and the box of the chunk itself.
-  for (int ch = wid; ch < nchunks; ch += nw) {
-    const int base = ch * kWave;
-    const int i = base + lane;
-    const bool valid = i < n;
-    const int c = valid ? cellOf[i] : -1;
-    const int cn = (i + 1 < n && lane < kWave - 1) ? cellOf[i + 1] : -2;
-    const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
-    bool owned = false;
-    if (last) owned = cellStart[c] >= base && cellStart[c + 1] <= base + kWave;
+    const int nw = gridDim.x * kWavesPerBlock;
+    const int nchunks = (n + kWave - 1) / kWave;
+    // (1) Per aligned 64-point chunk: boxes of the cells lying wholly inside it
+    // (segmented wave reduction) and the box of the chunk itself.
+    for (int ch = wid; ch < nchunks; ch += nw) {
+      const int base = ch * kWave;
+      const int i = base + lane;
+      const bool valid = i < n;
+      const int c = valid ? cellOf[i] : -1;
+      const int cn = (i + 1 < n && lane < kWave - 1) ? cellOf[i + 1] : -2;
+      const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
+      bool owned = false;
+      if (last) owned = cellStart[c] >= base && cellStart[c + 1] <= base + kWave;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
-      double a = x, b = x;
+      for (int k = 0; k < D; ++k) {
+        const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
+        double a = x, b = x;
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const double ua = __shfl_up(a, o, kWave);
-        const double ub = __shfl_up(b, o, kWave);
-        const int uc = __shfl_up(c, o, kWave);
-        if (lane >= o && uc == c) {
-          a = fmin(a, ua);
-          b = fmax(b, ub);
+        for (int o = 1; o < kWave; o <<= 1) {
+          const double ua = __shfl_up(a, o, kWave);
+          const double ub = __shfl_up(b, o, kWave);
+          const int uc = __shfl_up(c, o, kWave);
+          if (lane >= o && uc == c) {
+            a = fmin(a, ua);
+            b = fmax(b, ub);
+          }
+        }
+        if (owned) {
+          lo[(size_t)k * n + c] = a;
+          hi[(size_t)k * n + c] = b;
+        }
+        if (!only_if_split) {
+          const double ca = wave_min(valid ? x : __builtin_inf());
+          const double cb = wave_max(valid ? x : -__builtin_inf());
+          if (lane == 0) {
+            W.chunkLo[(size_t)k * W.chunkCap + ch] = ca;
+            W.chunkHi[(size_t)k * W.chunkCap + ch] = cb;
+          }
         }
       }
-      if (owned) {
-        lo[(size_t)k * n + c] = a;
-        hi[(size_t)k * n + c] = b;
+    }
+    // (2) Cells spanning more than one chunk: one wave per cell, U x 64 points per
+    // step with every load issued before the reduction, so a large cell costs a few
+    // load latencies (and no atomics).
+    constexpr int U = D <= 3 ? 8 : 4;
+    for (int c = wid; c < C; c += nw) {
+      const int s = cellStart[c], e = cellStart[c + 1];
+      if ((s >> 6) == ((e - 1) >> 6)) continue;  // inside one chunk: done in (1)
+      double a[D], b[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        a[k] = __builtin_inf();
+        b[k] = -__builtin_inf();
       }
-      if (!only_if_split) {
-        const double ca = wave_min(valid ? x : __builtin_inf());
-        const double cb = wave_max(valid ? x : -__builtin_inf());
+      for (int i0 = s; i0 < e; i0 += U * kWave) {
+        double x[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kWave + lane;
+#pragma unroll
+          for (int k = 0; k < D; ++k) x[u][k] = i < e ? W.X[(size_t)k * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool v = i0 + u * kWave + lane < e;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            a[k] = v ? fmin(a[k], x[u][k]) : a[k];
+            b[k] = v ? fmax(b[k], x[u][k]) : b[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double ra = wave_min(a[k]), rb = wave_max(b[k]);
         if (lane == 0) {
-          W.chunkLo[(size_t)k * W.chunkCap + ch] = ca;
-          W.chunkHi[(size_t)k * W.chunkCap + ch] = cb;
+          lo[(size_t)k * n + c] = ra;
+          hi[(size_t)k * n + c] = rb;
         }
       }
     }
-  }
-  // (2) Cells spanning more than one chunk: one wave per cell, U x 64 points per
-  // step with every load issued before the reduction, so a large cell costs a few
-  // load latencies (and no atomics).
-  constexpr int U = D <= 3 ? 8 : 4;
-  for (int c = wid; c < C; c += nw) {
-    const int s = cellStart[c], e = cellStart[c + 1];
-    if ((s >> 6) == ((e - 1) >> 6)) continue;  // inside one chunk: done in (1)
-    double a[D], b[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      a[k] = __builtin_inf();
-      b[k] = -__builtin_inf();
-    }
-    for (int i0 = s; i0 < e; i0 += U * kWave) {
-      double x[U][D];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kWave + lane;
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[u][k] = i < e ? W.X[(size_t)k * n + i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool v = i0 + u * kWave + lane < e;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          a[k] = v ? fmin(a[k], x[u][k]) : a[k];
-          b[k] = v ? fmax(b[k], x[u][k]) : b[k];
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double ra = wave_min(a[k]), rb = wave_max(b[k]);
-      if (lane == 0) {
-        lo[(size_t)k * n + c] = ra;
-        hi[(size_t)k * n + c] = rb;
-      }
-    }
-  }
+  });
 }
 
 // Sub-cell order for large cells: the leaves of the paper's per-cell quadtree
@@ -753,172 +821,176 @@ struct SubCode {
   }
 };
 
-template <int D>
-__global__ __launch_bounds__(kSubThreads) void k_subsort(Work W) {
-  static_assert(D <= 3, "sub-cell order is built for d <= 3 only");
-  constexpr int NW = kSubThreads / kWave;
-  constexpr int U = kSubUnroll;
-  __shared__ int s_off[1 << kSubMaxBits];
-  __shared__ uint32_t s_wsum[NW];
-  const GridDesc* g = W.desc;
-  const int nq = g->n_sub, n = W.n;
-  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-  // one float64 array of n per dimension (the float32 coordinates hold
-  // 4 n D >= 8 n bytes for d >= 2) and the moved input indices
-  double* tmp[3] = {reinterpret_cast<double*>(W.keyA), reinterpret_cast<double*>(W.keyB),
-                    reinterpret_cast<double*>(W.X32)};
-  int32_t* tperm = reinterpret_cast<int32_t*>(W.idxA);
-  for (int t = blockIdx.x; t < nq; t += gridDim.x) {
-    const int s = W.sublist[t];
-    const int c = W.cellOf[s];
-    const int e = W.cellStart[c + 1];
-    const int a = (s + kWave - 1) / kWave * kWave, b = e / kWave * kWave;
-    // f bits per dimension: about one Morton code per chunk
-    const int nck = (b - a) / kWave;
-    int lg = 0;
-    while ((1 << lg) < nck) ++lg;
-    SubCode<D> code;
-    code.f = max(1, min((lg + D - 1) / D, kSubMaxBits / D));
-    code.top = (1u << code.f) - 1u;
-    const int B = 1 << (code.f * D);
+template <int D, class WS>
+__global__ __launch_bounds__(kSubThreads) void k_subsort(WS ws) {
+  ws.each([&](const Work& W) {
+    static_assert(D <= 3, "sub-cell order is built for d <= 3 only");
+    constexpr int NW = kSubThreads / kWave;
+    constexpr int U = kSubUnroll;
+    __shared__ int s_off[1 << kSubMaxBits];
+    __shared__ uint32_t s_wsum[NW];
+    const GridDesc* g = W.desc;
+    const int nq = g->n_sub, n = W.n;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    // one float64 array of n per dimension (the float32 coordinates hold
+    // 4 n D >= 8 n bytes for d >= 2) and the moved input indices
+    double* tmp[3] = {reinterpret_cast<double*>(W.keyA), reinterpret_cast<double*>(W.keyB),
+                      reinterpret_cast<double*>(W.X32)};
+    int32_t* tperm = reinterpret_cast<int32_t*>(W.idxA);
+    for (int t = blockIdx.x; t < nq; t += gridDim.x) {
+      const int s = W.sublist[t];
+      const int c = W.cellOf[s];
+      const int e = W.cellStart[c + 1];
+      const int a = (s + kWave - 1) / kWave * kWave, b = e / kWave * kWave;
+      // f bits per dimension: about one Morton code per chunk
+      const int nck = (b - a) / kWave;
+      int lg = 0;
+      while ((1 << lg) < nck) ++lg;
+      SubCode<D> code;
+      code.f = max(1, min((lg + D - 1) / D, kSubMaxBits / D));
+      code.top = (1u << code.f) - 1u;
+      const int B = 1 << (code.f * D);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      code.lo[k] = W.tree.lo[0][(size_t)k * n + c];
-      const double ext = W.tree.hi[0][(size_t)k * n + c] - code.lo[k];
-      code.sc[k] = ext > 0.0 ? ldexp(1.0, code.f) / ext : 0.0;
-    }
-    for (int j = tid; j < B; j += kSubThreads) s_off[j] = 0;
-    __syncthreads();
-    // (1) points per code
-    for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
-      double x[U][D];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kSubThreads;
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[u][k] = i < b ? W.X[(size_t)k * n + i] : 0.0;
+      for (int k = 0; k < D; ++k) {
+        code.lo[k] = W.tree.lo[0][(size_t)k * n + c];
+        const double ext = W.tree.hi[0][(size_t)k * n + c] - code.lo[k];
+        code.sc[k] = ext > 0.0 ? ldexp(1.0, code.f) / ext : 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * kSubThreads < b) atomicAdd(&s_off[code(x[u])], 1);
-    }
-    __syncthreads();
-    // (2) first position of each code: exclusive prefix over the codes, each
-    // thread owning a run of B / kSubThreads of them
-    {
-      const int per = (B + kSubThreads - 1) / kSubThreads;
-      const int j0 = min(B, tid * per), j1 = min(B, j0 + per);
-      int run = 0;
-      for (int j = j0; j < j1; ++j) run += s_off[j];
-      const int incl = wave_incl_scan(run);
-      if (lane == kWave - 1) s_wsum[w] = (uint32_t)incl;
+      for (int j = tid; j < B; j += kSubThreads) s_off[j] = 0;
       __syncthreads();
-      int pre = a + incl - run;
-      for (int k = 0; k < w; ++k) pre += (int)s_wsum[k];
-      for (int j = j0; j < j1; ++j) {
-        const int v = s_off[j];
-        s_off[j] = pre;
-        pre += v;
+      // (1) points per code
+      for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
+        double x[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kSubThreads;
+#pragma unroll
+          for (int k = 0; k < D; ++k) x[u][k] = i < b ? W.X[(size_t)k * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i0 + u * kSubThreads < b) atomicAdd(&s_off[code(x[u])], 1);
       }
-    }
-    __syncthreads();
-    // (3) every point and its input index to its place in the temporaries
-    for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
-      int pm[U];
-      double x[U][D];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kSubThreads;
-        const bool ok = i < b;
-        pm[u] = ok ? W.perm[i] : 0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[u][k] = ok ? W.X[(size_t)k * n + i] : 0.0;
+      __syncthreads();
+      // (2) first position of each code: exclusive prefix over the codes, each
+      // thread owning a run of B / kSubThreads of them
+      {
+        const int per = (B + kSubThreads - 1) / kSubThreads;
+        const int j0 = min(B, tid * per), j1 = min(B, j0 + per);
+        int run = 0;
+        for (int j = j0; j < j1; ++j) run += s_off[j];
+        const int incl = wave_incl_scan(run);
+        if (lane == kWave - 1) s_wsum[w] = (uint32_t)incl;
+        __syncthreads();
+        int pre = a + incl - run;
+        for (int k = 0; k < w; ++k) pre += (int)s_wsum[k];
+        for (int j = j0; j < j1; ++j) {
+          const int v = s_off[j];
+          s_off[j] = pre;
+          pre += v;
+        }
       }
+      __syncthreads();
+      // (3) every point and its input index to its place in the temporaries
+      for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
+        int pm[U];
+        double x[U][D];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (i0 + u * kSubThreads >= b) continue;
-        const int t = atomicAdd(&s_off[code(x[u])], 1);
-        tperm[t] = pm[u];
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kSubThreads;
+          const bool ok = i < b;
+          pm[u] = ok ? W.perm[i] : 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) tmp[k][t] = x[u][k];
+          for (int k = 0; k < D; ++k) x[u][k] = ok ? W.X[(size_t)k * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (i0 + u * kSubThreads >= b) continue;
+          const int t = atomicAdd(&s_off[code(x[u])], 1);
+          tperm[t] = pm[u];
+#pragma unroll
+          for (int k = 0; k < D; ++k) tmp[k][t] = x[u][k];
+        }
       }
-    }
-    __syncthreads();
-    // (4) back into place, one wave per chunk, with the chunk's new box
-    constexpr int V = 4;
-    for (int ch0 = a / kWave + w * V; ch0 < b / kWave; ch0 += NW * V) {
-      int pm[V];
-      double x[V][D];
+      __syncthreads();
+      // (4) back into place, one wave per chunk, with the chunk's new box
+      constexpr int V = 4;
+      for (int ch0 = a / kWave + w * V; ch0 < b / kWave; ch0 += NW * V) {
+        int pm[V];
+        double x[V][D];
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int i = (ch0 + v) * kWave + lane;
-        const bool ok = i < b;
-        pm[v] = ok ? tperm[i] : 0;
+        for (int v = 0; v < V; ++v) {
+          const int i = (ch0 + v) * kWave + lane;
+          const bool ok = i < b;
+          pm[v] = ok ? tperm[i] : 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[v][k] = ok ? tmp[k][i] : 0.0;
-      }
+          for (int k = 0; k < D; ++k) x[v][k] = ok ? tmp[k][i] : 0.0;
+        }
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int ch = ch0 + v;
-        if (ch * kWave >= b) continue;
-        const int i = ch * kWave + lane;
-        W.perm[i] = pm[v];
-        if (W.inv) W.inv[pm[v]] = i;
+        for (int v = 0; v < V; ++v) {
+          const int ch = ch0 + v;
+          if (ch * kWave >= b) continue;
+          const int i = ch * kWave + lane;
+          W.perm[i] = pm[v];
+          if (W.inv) W.inv[pm[v]] = i;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          W.X[(size_t)k * n + i] = x[v][k];
-          const double mn = wave_min(x[v][k]), mx = wave_max(x[v][k]);
-          if (lane == 0) {
-            W.chunkLo[(size_t)k * W.chunkCap + ch] = mn;
-            W.chunkHi[(size_t)k * W.chunkCap + ch] = mx;
+          for (int k = 0; k < D; ++k) {
+            W.X[(size_t)k * n + i] = x[v][k];
+            const double mn = wave_min(x[v][k]), mx = wave_max(x[v][k]);
+            if (lane == 0) {
+              W.chunkLo[(size_t)k * W.chunkCap + ch] = mn;
+              W.chunkHi[(size_t)k * W.chunkCap + ch] = mx;
+            }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  });
 }
 
 // Diameter guard: D(lo, hi) <= E2 proves every pair in the cell is within eps
 // (monotone rounding; see box_sqdist).  The paper's claim that all points of a
 // cell are within eps holds in exact arithmetic only.
-template <int D>
-__global__ void k_cell_safe(Work W) {
-  GridDesc* g = W.desc;
-  const int C = g->n_cells, n = W.n;
-  int bad = 0;
-  double ext = 0.0;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-    double a[D], b[D];
+template <int D, class WS>
+__global__ void k_cell_safe(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    GridDesc* g = W.desc;
+    const int C = g->n_cells, n = W.n;
+    int bad = 0;
+    double ext = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+      double a[D], b[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      a[k] = W.tree.lo[0][(size_t)k * n + c];
-      b[k] = W.tree.hi[0][(size_t)k * n + c];
-    }
-    const bool uns = !(sqdist<D>(a, b) <= W.E2);
-    W.unsafe[c] = uns;
-    bad += uns;
-    // safe cells with at least sub_min points and two whole chunks inside them
-    // are queued for sub-cell order by their first sorted position, which the
-    // split of unsafe cells (into singletons, renumbering the cells) keeps
-    if (!uns && W.sub_min != kIntMax && g->fine_bits == 0) {
-      const int s = W.cellStart[c], e = W.cellStart[c + 1];
-      if (e - s >= W.sub_min && e / kWave - (s + kWave - 1) / kWave >= 2)
-        W.sublist[atomicAdd(&g->n_sub, 1)] = s;
-    }
-    // the extent bounds |coordinate - anchor| in the float32 filter; a cell that
-    // fails the guard becomes singletons, whose anchors are the points themselves
-    if (!uns) {
+      for (int k = 0; k < D; ++k) {
+        a[k] = W.tree.lo[0][(size_t)k * n + c];
+        b[k] = W.tree.hi[0][(size_t)k * n + c];
+      }
+      const bool uns = !(sqdist<D>(a, b) <= W.E2);
+      W.unsafe[c] = uns;
+      bad += uns;
+      // safe cells with at least sub_min points and two whole chunks inside them
+      // are queued for sub-cell order by their first sorted position, which the
+      // split of unsafe cells (into singletons, renumbering the cells) keeps
+      if (!uns && W.sub_min != kIntMax && g->fine_bits == 0) {
+        const int s = W.cellStart[c], e = W.cellStart[c + 1];
+        if (e - s >= W.sub_min && e / kWave - (s + kWave - 1) / kWave >= 2)
+          W.sublist[atomicAdd(&g->n_sub, 1)] = s;
+      }
+      // the extent bounds |coordinate - anchor| in the float32 filter; a cell that
+      // fails the guard becomes singletons, whose anchors are the points themselves
+      if (!uns) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
+        for (int k = 0; k < D; ++k) ext = fmax(ext, b[k] - a[k]);
+      }
     }
-  }
-  bad = wave_sum(bad);
-  ext = wave_max(ext);
-  if (lane_id() == 0 && bad) atomicAdd(&g->n_unsafe, bad);
-  // extents are >= 0, so their bit patterns order like the values
-  if (lane_id() == 0 && ext > 0.0)
-    atomicMax(&g->max_extent_bits, (unsigned long long)__double_as_longlong(ext));
+    bad = wave_sum(bad);
+    ext = wave_max(ext);
+    if (lane_id() == 0 && bad) atomicAdd(&g->n_unsafe, bad);
+    // extents are >= 0, so their bit patterns order like the values
+    if (lane_id() == 0 && ext > 0.0)
+      atomicMax(&g->max_extent_bits, (unsigned long long)__double_as_longlong(ext));
+  });
 }
 
 // Float32 filter thresholds (see decide32).  With u = 2^-24, v = 2^-53,
@@ -984,9 +1056,11 @@ DB_DEV void local32_part(const Work& W, double eps, int nwg, int bid) {
   }
 }
 
-template <int D>
-__global__ void k_local32(Work W, double eps) {
-  local32_part<D>(W, eps, (int)gridDim.x, (int)blockIdx.x);
+template <int D, class WS>
+__global__ void k_local32(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    local32_part<D>(W, W.eps, (int)gridDim.x, (int)blockIdx.x);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -998,53 +1072,10 @@ DB_DEV int level_count(int C, int l) {
   return (int)c;
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_tree_level(Work W, int l) {
-  const int C = W.desc->n_cells;
-  const int nchild = level_count(C, l - 1);
-  const int nnode = (nchild + 63) >> 6;
-  const double* clo = W.tree.lo[l - 1];
-  const double* chi = W.tree.hi[l - 1];
-  const int cs = W.tree.cap[l - 1];
-  double* plo = const_cast<double*>(W.tree.lo[l]);
-  double* phi = const_cast<double*>(W.tree.hi[l]);
-  float* cflo = const_cast<float*>(W.tree.flo[l - 1]);
-  float* cfhi = const_cast<float*>(W.tree.fhi[l - 1]);
-  float* pflo = const_cast<float*>(W.tree.flo[l]);
-  float* pfhi = const_cast<float*>(W.tree.fhi[l]);
-  const int ps = W.tree.cap[l];
-  const int lane = lane_id();
-  for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < nnode;
-       j += gridDim.x * kWavesPerBlock) {
-    const int ch = j * 64 + lane;
-    const bool v = ch < nchild;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double ca = v ? clo[(size_t)k * cs + ch] : __builtin_inf();
-      const double cb = v ? chi[(size_t)k * cs + ch] : -__builtin_inf();
-      if (l == 1 && v) {  // float copies of the cell boxes
-        cflo[(size_t)k * cs + ch] = __double2float_rd(ca);
-        cfhi[(size_t)k * cs + ch] = __double2float_ru(cb);
-      }
-      const double a = wave_min(ca);
-      const double b = wave_max(cb);
-      if (lane == 0) {
-        plo[(size_t)k * ps + j] = a;
-        phi[(size_t)k * ps + j] = b;
-        pflo[(size_t)k * ps + j] = __double2float_rd(a);
-        pfhi[(size_t)k * ps + j] = __double2float_ru(b);
-      }
-    }
-  }
-}
-
-// Levels l0 .. top in one workgroup (they hold few nodes: C / 64^l0 at most), level
-// after level, instead of one launch each.
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
-  const int C = W.desc->n_cells;
-  const int lane = lane_id();
-  for (int l = l0; l <= kTreeLevels; ++l) {
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_tree_level(WS ws, int l) {
+  ws.each_wave([&](const Work& W) {
+    const int C = W.desc->n_cells;
     const int nchild = level_count(C, l - 1);
     const int nnode = (nchild + 63) >> 6;
     const double* clo = W.tree.lo[l - 1];
@@ -1052,19 +1083,26 @@ __global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
     const int cs = W.tree.cap[l - 1];
     double* plo = const_cast<double*>(W.tree.lo[l]);
     double* phi = const_cast<double*>(W.tree.hi[l]);
+    float* cflo = const_cast<float*>(W.tree.flo[l - 1]);
+    float* cfhi = const_cast<float*>(W.tree.fhi[l - 1]);
     float* pflo = const_cast<float*>(W.tree.flo[l]);
     float* pfhi = const_cast<float*>(W.tree.fhi[l]);
     const int ps = W.tree.cap[l];
-    double top_lo[D], top_hi[D];  // the box of node 0 (wave 0, lane 0)
-    for (int j = threadIdx.x / kWave; j < nnode; j += kWavesPerBlock) {
+    const int lane = lane_id();
+    for (int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < nnode;
+         j += gridDim.x * kWavesPerBlock) {
       const int ch = j * 64 + lane;
       const bool v = ch < nchild;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
-        const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
-        top_lo[k] = a;
-        top_hi[k] = b;
+        const double ca = v ? clo[(size_t)k * cs + ch] : __builtin_inf();
+        const double cb = v ? chi[(size_t)k * cs + ch] : -__builtin_inf();
+        if (l == 1 && v) {  // float copies of the cell boxes
+          cflo[(size_t)k * cs + ch] = __double2float_rd(ca);
+          cfhi[(size_t)k * cs + ch] = __double2float_ru(cb);
+        }
+        const double a = wave_min(ca);
+        const double b = wave_max(cb);
         if (lane == 0) {
           plo[(size_t)k * ps + j] = a;
           phi[(size_t)k * ps + j] = b;
@@ -1073,26 +1111,66 @@ __global__ __launch_bounds__(kBlock) void k_tree_tail(Work W, int l0) {
         }
       }
     }
-    if (nnode == 1) {
-      // every level above holds this one node with the same box: written directly,
-      // without a round of loads and reductions per level
-      if (threadIdx.x == 0) {
-        for (int u = l + 1; u <= kTreeLevels; ++u) {
-          const int us = W.tree.cap[u];
+  });
+}
+
+// Levels l0 .. top in one workgroup (they hold few nodes: C / 64^l0 at most), level
+// after level, instead of one launch each.
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_tree_tail(WS ws, int l0) {
+  ws.each([&](const Work& W) {
+    const int C = W.desc->n_cells;
+    const int lane = lane_id();
+    for (int l = l0; l <= kTreeLevels; ++l) {
+      const int nchild = level_count(C, l - 1);
+      const int nnode = (nchild + 63) >> 6;
+      const double* clo = W.tree.lo[l - 1];
+      const double* chi = W.tree.hi[l - 1];
+      const int cs = W.tree.cap[l - 1];
+      double* plo = const_cast<double*>(W.tree.lo[l]);
+      double* phi = const_cast<double*>(W.tree.hi[l]);
+      float* pflo = const_cast<float*>(W.tree.flo[l]);
+      float* pfhi = const_cast<float*>(W.tree.fhi[l]);
+      const int ps = W.tree.cap[l];
+      double top_lo[D], top_hi[D];  // the box of node 0 (wave 0, lane 0)
+      for (int j = threadIdx.x / kWave; j < nnode; j += kWavesPerBlock) {
+        const int ch = j * 64 + lane;
+        const bool v = ch < nchild;
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const_cast<double*>(W.tree.lo[u])[(size_t)k * us] = top_lo[k];
-            const_cast<double*>(W.tree.hi[u])[(size_t)k * us] = top_hi[k];
-            const_cast<float*>(W.tree.flo[u])[(size_t)k * us] = __double2float_rd(top_lo[k]);
-            const_cast<float*>(W.tree.fhi[u])[(size_t)k * us] = __double2float_ru(top_hi[k]);
+        for (int k = 0; k < D; ++k) {
+          const double a = wave_min(v ? clo[(size_t)k * cs + ch] : __builtin_inf());
+          const double b = wave_max(v ? chi[(size_t)k * cs + ch] : -__builtin_inf());
+          top_lo[k] = a;
+          top_hi[k] = b;
+          if (lane == 0) {
+            plo[(size_t)k * ps + j] = a;
+            phi[(size_t)k * ps + j] = b;
+            pflo[(size_t)k * ps + j] = __double2float_rd(a);
+            pfhi[(size_t)k * ps + j] = __double2float_ru(b);
           }
         }
       }
-      return;
+      if (nnode == 1) {
+        // every level above holds this one node with the same box: written directly,
+        // without a round of loads and reductions per level
+        if (threadIdx.x == 0) {
+          for (int u = l + 1; u <= kTreeLevels; ++u) {
+            const int us = W.tree.cap[u];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+              const_cast<double*>(W.tree.lo[u])[(size_t)k * us] = top_lo[k];
+              const_cast<double*>(W.tree.hi[u])[(size_t)k * us] = top_hi[k];
+              const_cast<float*>(W.tree.flo[u])[(size_t)k * us] = __double2float_rd(top_lo[k]);
+              const_cast<float*>(W.tree.fhi[u])[(size_t)k * us] = __double2float_ru(top_hi[k]);
+            }
+          }
+        }
+        return;
+      }
+      __threadfence_block();
+      __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
-  }
+  });
 }
 
 }  // namespace db

@@ -177,52 +177,54 @@ struct SparseCountVisitor {
   }
 };
 
-template <int D, bool F32>
-__global__ __launch_bounds__(kBlock) void k_markcore_sparse(Work W) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
-  const int C = W.desc->n_cells, n = W.n;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int cap = W.count_cap;
-  const double lim = sqrt(W.E2);
-  Counters tot;
-  const UnitRange R = xcd_units((n + kWave - 1) / kWave);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int i = (int)u * kWave + lane;
-    const bool exists = i < n;
-    int c = 0, m = 0;
-    if (exists) {
-      c = W.cellOf[i];
-      m = W.cellStart[c + 1] - W.cellStart[c];
+template <int D, bool F32, class WS>
+__global__ __launch_bounds__(kBlock) void k_markcore_sparse(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ double s_dist[kWavesPerBlock][(kTreeLevels + 2) * 64];
+    const int C = W.desc->n_cells, n = W.n;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int cap = W.count_cap;
+    const double lim = sqrt(W.E2);
+    Counters tot;
+    const UnitRange R = xcd_units((n + kWave - 1) / kWave);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int i = (int)u * kWave + lane;
+      const bool exists = i < n;
+      int c = 0, m = 0;
+      if (exists) {
+        c = W.cellOf[i];
+        m = W.cellStart[c + 1] - W.cellStart[c];
+      }
+      // a point of a cell of at least cap points has them within eps (the cell is safe)
+      if (exists && m >= cap) W.cnt[i] = m;
+      SparseCountVisitor<D, F32> v;
+      v.W = &W;
+      v.F = Flat{s_pref[w], s_start[w]};
+      v.B.load(W, exists ? i : -1, c);
+      v.tin = W.desc->tin;
+      v.tout = W.desc->tout;
+      const bool need = exists && m < cap;
+      uint64_t rest = ballot(need);
+      while (rest) {
+        const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
+        rest &= ~batch;
+        const bool in = (batch >> lane) & 1ull;
+        v.cnt = m;
+        v.pending = batch;
+        Query<D> qb;
+        qb.E2 = W.E2;
+        v.B.box(in, qb);
+        walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
+        if (in) W.cnt[i] = v.cnt;
+      }
+      tot.add(v.ctr);
     }
-    // a point of a cell of at least cap points has them within eps (the cell is safe)
-    if (exists && m >= cap) W.cnt[i] = m;
-    SparseCountVisitor<D, F32> v;
-    v.W = &W;
-    v.F = Flat{s_pref[w], s_start[w]};
-    v.B.load(W, exists ? i : -1, c);
-    v.tin = W.desc->tin;
-    v.tout = W.desc->tout;
-    const bool need = exists && m < cap;
-    uint64_t rest = ballot(need);
-    while (rest) {
-      const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
-      rest &= ~batch;
-      const bool in = (batch >> lane) & 1ull;
-      v.cnt = m;
-      v.pending = batch;
-      Query<D> qb;
-      qb.E2 = W.E2;
-      v.B.box(in, qb);
-      walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
-      if (in) W.cnt[i] = v.cnt;
-    }
-    tot.add(v.ctr);
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -298,50 +300,52 @@ struct SparseLinkVisitor {
   }
 };
 
-template <int D, bool F32, bool WARM>
-__global__ __launch_bounds__(kBlock) void k_bcp_sparse(Work W) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  const int C = W.desc->n_cells, n = W.n;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const bool gained_only = WARM && W.prev_core_count != nullptr;
-  const double lim = sqrt(W.E2b);
-  Counters tot;
-  const UnitRange R = xcd_units((n + kWave - 1) / kWave);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int i = (int)u * kWave + lane;
-    bool need = i < n && (W.coreS[i] & W.core_mask) != 0;
-    int c = 0;
-    if (need) {
-      c = W.cellOf[i];
-      if (gained_only) need = W.coreCount[c] > W.prev_core_count[c];
+template <int D, bool F32, bool WARM, class WS>
+__global__ __launch_bounds__(kBlock) void k_bcp_sparse(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    const int C = W.desc->n_cells, n = W.n;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const bool gained_only = WARM && W.prev_core_count != nullptr;
+    const double lim = sqrt(W.E2b);
+    Counters tot;
+    const UnitRange R = xcd_units((n + kWave - 1) / kWave);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int i = (int)u * kWave + lane;
+      bool need = i < n && (W.coreS[i] & W.core_mask) != 0;
+      int c = 0;
+      if (need) {
+        c = W.cellOf[i];
+        if (gained_only) need = W.coreCount[c] > W.prev_core_count[c];
+      }
+      uint64_t rest = ballot(need);
+      if (!rest) continue;
+      SparseLinkVisitor<D, F32> v;
+      v.W = &W;
+      v.F = Flat{s_pref[w], s_start[w]};
+      v.B.load(W, need ? i : -1, c);
+      v.any_other = gained_only;
+      v.tin = W.desc->tinb;
+      v.tout = W.desc->toutb;
+      while (rest) {
+        const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
+        rest &= ~batch;
+        const bool in = (batch >> lane) & 1ull;
+        v.active = batch;
+        v.root = in ? uf_find(W.parent, c) : -1;
+        v.hmax = wave_max(in ? c : -1);
+        Query<D> qb;
+        qb.E2 = W.E2b;
+        v.B.box(in, qb);
+        walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], nullptr});
+      }
+      tot.add(v.ctr);
     }
-    uint64_t rest = ballot(need);
-    if (!rest) continue;
-    SparseLinkVisitor<D, F32> v;
-    v.W = &W;
-    v.F = Flat{s_pref[w], s_start[w]};
-    v.B.load(W, need ? i : -1, c);
-    v.any_other = gained_only;
-    v.tin = W.desc->tinb;
-    v.tout = W.desc->toutb;
-    while (rest) {
-      const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
-      rest &= ~batch;
-      const bool in = (batch >> lane) & 1ull;
-      v.active = batch;
-      v.root = in ? uf_find(W.parent, c) : -1;
-      v.hmax = wave_max(in ? c : -1);
-      Query<D> qb;
-      qb.E2 = W.E2b;
-      v.B.box(in, qb);
-      walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], nullptr});
-    }
-    tot.add(v.ctr);
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -400,48 +404,55 @@ struct SparseBorderVisitor {
   }
 };
 
-template <int D, bool F32>
-__global__ __launch_bounds__(kBlock) void k_border_sparse(Work W) {
-  __shared__ int s_pref[kWavesPerBlock][kWave + 1];
-  __shared__ int s_start[kWavesPerBlock][kWave];
-  __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
-  __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-  const int C = W.desc->n_cells, n = W.n;
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const double lim = sqrt(W.E2);
-  Counters tot;
-  const UnitRange R = xcd_units((n + kWave - 1) / kWave);
-  for (long long u = R.first; u < R.end; u += R.step) {
-    const int i = (int)u * kWave + lane;
-    const bool need = i < n && (W.coreS[i] & W.core_mask) == 0;
-    uint64_t rest = ballot(need);
-    if (!rest) continue;
-    int c = 0, own = kIntMax;
-    if (need) {
-      c = W.cellOf[i];
-      own = W.coreCount[c] > 0 ? W.cellLabel[c] : kIntMax;
+template <int D, bool F32, class WS>
+__global__ __launch_bounds__(kBlock) void k_border_sparse(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    __shared__ int s_pref[kWavesPerBlock][kWave + 1];
+    __shared__ int s_start[kWavesPerBlock][kWave];
+    __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
+    __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
+    const int C = W.desc->n_cells, n = W.n;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const double lim = sqrt(W.E2);
+    Counters tot;
+    const UnitRange R = xcd_units((n + kWave - 1) / kWave);
+    for (long long u = R.first; u < R.end; u += R.step) {
+      const int i = (int)u * kWave + lane;
+      bool need = i < n && (W.coreS[i] & W.core_mask) == 0;
+      int c = 0, own = kIntMax;
+      if (need) {
+        c = W.cellOf[i];
+        own = W.coreCount[c] > 0 ? W.cellLabel[c] : kIntMax;
+        // no neighbour outside its cell (exact count of a non-core point, |c| included)
+        if (W.cnt[i] == W.cellStart[c + 1] - W.cellStart[c]) {
+          W.blabel[i] = own == kIntMax ? -1 : own;
+          need = false;
+        }
+      }
+      uint64_t rest = ballot(need);
+      if (!rest) continue;
+      SparseBorderVisitor<D, F32> v;
+      v.W = &W;
+      v.F = Flat{s_pref[w], s_start[w]};
+      v.B.load(W, need ? i : -1, c);
+      v.tin = W.desc->tin;
+      v.tout = W.desc->tout;
+      while (rest) {
+        const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
+        rest &= ~batch;
+        const bool in = (batch >> lane) & 1ull;
+        v.active = batch;
+        v.best = own;
+        Query<D> qb;
+        qb.E2 = W.E2;
+        v.B.box(in, qb);
+        walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], nullptr});
+        if (in) W.blabel[i] = v.best == kIntMax ? -1 : v.best;
+      }
+      tot.add(v.ctr);
     }
-    SparseBorderVisitor<D, F32> v;
-    v.W = &W;
-    v.F = Flat{s_pref[w], s_start[w]};
-    v.B.load(W, need ? i : -1, c);
-    v.tin = W.desc->tin;
-    v.tout = W.desc->tout;
-    while (rest) {
-      const uint64_t batch = compact_batch<D>(v.B.p, (rest >> lane) & 1ull, lim);
-      rest &= ~batch;
-      const bool in = (batch >> lane) & 1ull;
-      v.active = batch;
-      v.best = own;
-      Query<D> qb;
-      qb.E2 = W.E2;
-      v.B.box(in, qb);
-      walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], nullptr});
-      if (in) W.blabel[i] = v.best == kIntMax ? -1 : v.best;
-    }
-    tot.add(v.ctr);
-  }
-  tot.wave_flush(W.desc);
+    tot.wave_flush(W.desc);
+  });
 }
 
 }  // namespace db
