@@ -10,13 +10,13 @@ Cases (names say workload, size, eps and minPts):
 * the 2D blobs and the 1M-point 3D spreader;
 * both 2M-point mixtures (5D and 7D) at eps 1.5, 2 and 3;
 * the 10M-point 3D sweep cloud at every eps and minPts of the sweep (about 2, 5.5,
-  13 and 35 minutes per setting at eps 200, 400, 800 and 1600);
+  13 and 16 minutes per setting at eps 200, 400, 800 and 1600 on 8 cores);
 * every cloud of the 256-cloud batch (one record holding one hash per cloud).
 
 The file is updated case by case, so a long run can be split (``--only PREFIX``)
 and resumed (cases already present are skipped unless ``--redo``).
 
-Run:  python tests/golden/make_full_size_hashes.py   (about four hours on 8 cores,
+Run:  python tests/golden/make_full_size_hashes.py   (about three hours on 8 cores,
 most of it the sweep cloud at eps 800 and 1600)
 """
 
