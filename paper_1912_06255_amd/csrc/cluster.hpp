@@ -481,12 +481,28 @@ struct MarkCoreVisitor {
   uint64_t pending;  // points of the batch still below minPts
   int smask, part;   // this wave tests every (smask + 1)-th candidate chunk, from part
   int chunk_no;
+  int flushed;       // split waves: how much of cnt this lane has added to W->cnt so far
   double p[D];       // lane t: coordinates of point ps + t (float64 mode)
   float ap[D];       // lane t: cell-local float32 coordinates (filter mode)
   double ag[D];      // anchor of g (filter mode)
   float tin, tout;
   int lm;            // neighbour cells of at least lm points are taken by chunk boxes
   Counters ctr;
+
+  // Split waves add their shares to the point's count as they go (one atomic per
+  // pending point and chunk), so a point stops once the shares of all its waves
+  // together reach the cap, not only when this wave's own share does.
+  DB_DEV void publish() {
+    if (!smask) return;
+    const int lane = lane_id();
+    const bool on = ((pending >> lane) & 1ull) && cnt > flushed;
+    int total = 0;
+    if (on) {
+      total = atomicAdd(&W->cnt[ps + lane], cnt - flushed) + (cnt - flushed);
+      flushed = cnt;
+    }
+    pending &= ~ballot(on && total >= W->count_cap);
+  }
 
   // A large neighbour cell h in sub-cell order, by its aligned 64-point chunks
   // (the leaves of the paper's per-cell quadtree): a chunk whose box lies wholly
@@ -545,6 +561,7 @@ struct MarkCoreVisitor {
         }
       }
       pending &= ~ballot(cnt >= W->count_cap);
+      publish();
       if (!pending) return true;
     }
     return false;
@@ -636,6 +653,7 @@ struct MarkCoreVisitor {
         const int ct = bcast(cnt, t);
         if (ct >= W->count_cap) pending &= ~(1ull << t);
       }
+      publish();
       if (!pending) return true;
     }
     return false;
@@ -661,8 +679,9 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
     const int n = W.n;
     const int cap = W.count_cap;
     // Waves per cell: the candidate chunks of a cell's walk are dealt out to split
-    // waves, which add their counts (cnt is zeroed by k_keys); a wave stops when its
-    // own share reaches the cap, so every count is exact or at least the cap.
+    // waves, which add their counts (cnt is zeroed by k_keys) as they go; a wave stops
+    // with a point when its own share, or the sum added so far by all of them,
+    // reaches the cap, so every count is exact or at least the cap.
     static_assert((kMarkSplit & (kMarkSplit - 1)) == 0, "split must be a power of two");
     const int sh =
         (D <= 3 && (long long)n >= (long long)kMarkSplitMean * C) ? __builtin_ctz(kMarkSplit) : 0;
@@ -694,6 +713,7 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
         v.smask = split - 1;
         v.part = part;
         v.chunk_no = 0;
+        v.flushed = part == 0 ? 0 : m;  // (every wave's cnt starts at |g|; part 0 adds it)
         v.tin = W.desc->tin;
         v.tout = W.desc->tout;
 #pragma unroll
@@ -710,7 +730,7 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
         walk_from_list<D>(W, C, g, q, v, WalkStack{s_m[w], s_cb[w], s_dist[w]});
         if (lane < v.pm) {
           if (split == 1) W.cnt[ps + lane] = v.cnt;
-          else atomicAdd(&W.cnt[ps + lane], part == 0 ? v.cnt : v.cnt - m);
+          else if (v.cnt > v.flushed) atomicAdd(&W.cnt[ps + lane], v.cnt - v.flushed);
         }
         tot.add(v.ctr);
       }
