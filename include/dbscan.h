@@ -344,8 +344,8 @@ int dbscan_membership(dbscan_ctx *ctx, int64_t *offsets, int32_t *ids, int64_t i
  *                bits (0 = fine; DBSCAN_STATUS_NONFINITE = a coordinate is NaN
  *                or infinite, outputs undefined) when the stream reaches the
  *                end of the call
- * Limit: the call's scratch, about (80 + 37 d) bytes per point plus a few KiB,
- * must fit the array: n up to 571,519 points in 1D, 351,744 in 3D and 179,332
+ * Limit: the call's scratch, about (80 + 38 d) bytes per point plus a few KiB,
+ * must fit the array: n up to 569,088 points in 1D, 348,992 in 3D and 177,432
  * in 8D.  Larger inputs return DBSCAN_ETOOLARGE before any work is queued.
  * Argument errors return DBSCAN_EINVAL as for dbscan().
  */

@@ -132,6 +132,7 @@ size_t layout(char* base, int64_t n, int d, Work* W, int slots = 1, bool keep_ke
   w.chunkCap = (int)ceil_div(n, 64);
   w.chunkLo = c.take<double>((int64_t)w.chunkCap * d);
   w.chunkHi = c.take<double>((int64_t)w.chunkCap * d);
+  w.runBox = c.take<double>((int64_t)w.chunkCap * d * 4);
   w.perm = c.take<int32_t>(n);
   w.cellOf = c.take<int32_t>(n);
   w.cellStart = c.take<int32_t>(n + 1);
@@ -299,10 +300,12 @@ void stage_grid_back(const Work& W, const WS& ws, hipStream_t s, const Marks& ma
   const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
   const unsigned tiles = (unsigned)ceil_div(n, kTile);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(ws, 0);
+  k_cell_span<D><<<gc, kBlock, 0, s>>>(ws, 0);
   k_cell_safe<D><<<gp, kBlock, 0, s>>>(ws);
   // cells that fail the float64 diameter guard become singletons
   k_cells<D><<<tiles, kBlock, 0, s>>>(ws, 1);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(ws, 1);
+  k_cell_span<D><<<gc, kBlock, 0, s>>>(ws, 1);
   if constexpr (D <= 3)
     if (subsort && W.sub_min != kIntMax) k_subsort<D><<<kSubBlocks, kSubThreads, 0, s>>>(ws);
   mark(5);

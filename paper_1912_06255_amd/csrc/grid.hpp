@@ -103,6 +103,8 @@ struct Work {
   float* X32;         // [D][n] float32 coordinates relative to the cell anchor (filter mode)
   double* chunkLo;    // [D][chunkCap] box of each aligned 64-point chunk of X
   double* chunkHi;
+  double* runBox;     // [4][D][chunkCap] boxes of each chunk's first and last cell runs
+                      // (first lo, first hi, last lo, last hi)
   int chunkCap;
   int32_t* perm;      // sorted position -> input index
   int32_t* inv;       // input index -> sorted position (kept only when several settings share a grid)
@@ -703,8 +705,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
     }
     const int nw = gridDim.x * kWavesPerBlock;
     const int nchunks = (n + kWave - 1) / kWave;
-    // (1) Per aligned 64-point chunk: boxes of the cells lying wholly inside it
-    // (segmented wave reduction) and the box of the chunk itself.
+    const size_t rc = (size_t)D * W.chunkCap;
+    // Per aligned 64-point chunk: boxes of the cells lying wholly inside it
+    // (segmented wave reduction), the box of the chunk itself, and the boxes of its
+    // first and last cell runs, from which k_cell_span builds the boxes of the cells
+    // that span several chunks.
     for (int ch = wid; ch < nchunks; ch += nw) {
       const int base = ch * kWave;
       const int i = base + lane;
@@ -712,6 +717,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
       const int c = valid ? cellOf[i] : -1;
       const int cn = (i + 1 < n && lane < kWave - 1) ? cellOf[i + 1] : -2;
       const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
+      // (the shuffle runs on every lane: a lane it reads from must be active)
+      const int c_first = __shfl(c, 0, kWave);
+      const bool first_run = last && c == c_first;
       bool owned = false;
       if (last) owned = cellStart[c] >= base && cellStart[c + 1] <= base + kWave;
 #pragma unroll
@@ -732,45 +740,70 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
           lo[(size_t)k * n + c] = a;
           hi[(size_t)k * n + c] = b;
         }
+        const size_t r = (size_t)k * W.chunkCap + ch;
+        if (first_run) {
+          W.runBox[r] = a;
+          W.runBox[rc + r] = b;
+        }
+        if (lane == kWave - 1) {  // (the last run of a chunk ends at its last lane)
+          W.runBox[2 * rc + r] = a;
+          W.runBox[3 * rc + r] = b;
+        }
         if (!only_if_split) {
           const double ca = wave_min(valid ? x : __builtin_inf());
           const double cb = wave_max(valid ? x : -__builtin_inf());
           if (lane == 0) {
-            W.chunkLo[(size_t)k * W.chunkCap + ch] = ca;
-            W.chunkHi[(size_t)k * W.chunkCap + ch] = cb;
+            W.chunkLo[r] = ca;
+            W.chunkHi[r] = cb;
           }
         }
       }
     }
-    // (2) Cells spanning more than one chunk: one wave per cell, U x 64 points per
-    // step with every load issued before the reduction, so a large cell costs a few
-    // load latencies (and no atomics).
-    constexpr int U = D <= 3 ? 8 : 4;
+
+  });
+}
+
+// Boxes of the cells that span more than one 64-point chunk (after k_cell_box, which
+// wrote every chunk's box and the boxes of its first and last cell runs): the last
+// run of the cell's first chunk, the whole chunks inside it and the first run of its
+// last chunk.  One wave per cell, 64 chunk boxes per step, so a cell of 128k points
+// costs 32 steps of loads instead of a pass over its points.
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_cell_span(WS ws, int only_if_split) {
+  ws.each_wave([&](const Work& W) {
+    const GridDesc* g = W.desc;
+    if (only_if_split && g->n_unsafe == 0) return;
+    const int n = W.n;
+    const int C = g->n_cells;
+    double* lo = const_cast<double*>(W.tree.lo[0]);
+    double* hi = const_cast<double*>(W.tree.hi[0]);
+    const int lane = lane_id();
+    const int wid = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int nw = gridDim.x * kWavesPerBlock;
+    const size_t cap = W.chunkCap;
+    const size_t rc = (size_t)D * cap;
     for (int c = wid; c < C; c += nw) {
-      const int s = cellStart[c], e = cellStart[c + 1];
-      if ((s >> 6) == ((e - 1) >> 6)) continue;  // inside one chunk: done in (1)
+      const int s = W.cellStart[c], e = W.cellStart[c + 1];
+      const int c0 = s >> 6, c1 = (e - 1) >> 6;
+      if (c0 == c1) continue;  // inside one chunk: done by k_cell_box
       double a[D], b[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         a[k] = __builtin_inf();
         b[k] = -__builtin_inf();
       }
-      for (int i0 = s; i0 < e; i0 += U * kWave) {
-        double x[U][D];
+      if (lane == 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kWave + lane;
-#pragma unroll
-          for (int k = 0; k < D; ++k) x[u][k] = i < e ? W.X[(size_t)k * n + i] : 0.0;
+        for (int k = 0; k < D; ++k) {
+          a[k] = fmin(W.runBox[2 * rc + k * cap + c0], W.runBox[k * cap + c1]);
+          b[k] = fmax(W.runBox[3 * rc + k * cap + c0], W.runBox[rc + k * cap + c1]);
         }
+      }
+      for (int j = c0 + 1 + lane; j < c1; j += kWave) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool v = i0 + u * kWave + lane < e;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            a[k] = v ? fmin(a[k], x[u][k]) : a[k];
-            b[k] = v ? fmax(b[k], x[u][k]) : b[k];
-          }
+        for (int k = 0; k < D; ++k) {
+          a[k] = fmin(a[k], W.chunkLo[k * cap + j]);
+          b[k] = fmax(b[k], W.chunkHi[k * cap + j]);
         }
       }
 #pragma unroll

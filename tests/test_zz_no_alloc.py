@@ -24,8 +24,8 @@ def _fn():
 def test_noalloc_size_limit_refused_on_host():
     f = _fn()
     # refused before any HIP call (so this runs without a GPU)
-    assert f(1, 351_745, 3, 1.0, 5, 0, 1, 1, None, None) == binding.ETOOLARGE
-    assert f(1, 179_333, 8, 1.0, 5, 0, 1, 1, None, None) == binding.ETOOLARGE
+    assert f(1, 348_993, 3, 1.0, 5, 0, 1, 1, None, None) == binding.ETOOLARGE
+    assert f(1, 177_433, 8, 1.0, 5, 0, 1, 1, None, None) == binding.ETOOLARGE
     assert f(None, 100, 3, 1.0, 5, 0, None, None, None, None) == binding.EINVAL
     assert f(1, 100, 9, 1.0, 5, 0, 1, 1, None, None) == binding.EINVAL
     assert f(1, 100, 3, 1.0, 5, 7, 1, 1, None, None) == binding.EINVAL
