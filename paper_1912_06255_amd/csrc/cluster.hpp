@@ -36,7 +36,10 @@ constexpr int kMarkSplit = DB_MARK_SPLIT;
 // ... when the grid holds at least this many points per cell on average.  In
 // sparser grids every split wave would repeat a walk that finds little to share
 // (3D clouds of 1.5 points per cell: 84 -> 17.5 ms of MarkCore with one wave).
-constexpr int kMarkSplitMean = 32;
+#ifndef DB_MARK_SPLIT_MEAN
+#define DB_MARK_SPLIT_MEAN 32
+#endif
+constexpr int kMarkSplitMean = DB_MARK_SPLIT_MEAN;
 // Sparse grids (sparse.hpp): MarkCore, ClusterCore and ClusterBorder can instead batch
 // the points of consecutive cells per tree walk (Work::sparse_mode 1, chosen by the
 // host; the per-cell kernels below are then not launched).

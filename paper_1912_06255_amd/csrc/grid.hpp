@@ -696,7 +696,6 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
     // after a split the new cells are read from the second arrays, which are also
     // copied over the first ones here
     const int32_t* cellOf = only_if_split ? W.cellOf2 : W.cellOf;
-    const int32_t* cellStart = only_if_split ? W.cellStart2 : W.cellStart;
     if (only_if_split) {
       for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
         if (i < n) W.cellOf[i] = W.cellOf2[i];
@@ -716,15 +715,23 @@ __global__ __launch_bounds__(kBlock) void k_cell_box(WS ws, int only_if_split) {
       const bool valid = i < n;
       const int c = valid ? cellOf[i] : -1;
       const int cn = (i + 1 < n && lane < kWave - 1) ? cellOf[i + 1] : -2;
+      // the cells just before and just after the chunk (one load each for the wave)
+      const int before = base > 0 ? cellOf[base - 1] : -1;
+      const int after = base + kWave < n ? cellOf[base + kWave] : -1;
+      double xs[D];  // every load issued before the first store
+#pragma unroll
+      for (int k = 0; k < D; ++k) xs[k] = valid ? W.X[(size_t)k * n + i] : 0.0;
       const bool last = valid && (lane == kWave - 1 || i + 1 >= n || cn != c);
       // (the shuffle runs on every lane: a lane it reads from must be active)
       const int c_first = __shfl(c, 0, kWave);
       const bool first_run = last && c == c_first;
-      bool owned = false;
-      if (last) owned = cellStart[c] >= base && cellStart[c + 1] <= base + kWave;
+      // a run lies wholly inside the chunk unless it is the first run and its cell
+      // began before the chunk, or it is the last run and its cell goes on after it
+      const bool owned = last && (!first_run || c != before) &&
+                         (lane < kWave - 1 || c != after);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const double x = valid ? W.X[(size_t)k * n + i] : 0.0;
+        const double x = xs[k];
         double a = x, b = x;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
