@@ -55,9 +55,12 @@ def test_step_bytes_model():
     items = [(X, [(1.0, 5), (1.0, 10), (2.0, 5)])]
     assert bench.step_algorithmic_bytes(items, True) == 1000 * (2 * (12 * 3 + 28) + 3 * (12 * 3 + 5))
     assert bench.step_algorithmic_bytes(items, False) == 1000 * (2 * (16 * 3 + 24) + 3 * (24 * 3 + 5))
-    # grid phases once per eps, the others once per setting
+    # grid phases once per eps, the others once per setting; ClusterCore runs cold once
+    # per eps and warm-started for the other settings of that eps
     assert bench.phase_algorithmic_bytes("keys", items, True) == 2 * 1000 * (8 * 3 + 12)
-    assert bench.phase_algorithmic_bytes("cluster_core", items, True) == 3 * 1000 * (4 * 3 + 1)
+    assert bench.phase_algorithmic_bytes("cluster_core", items, True) == 2 * 1000 * (4 * 3 + 1)
+    assert bench.phase_algorithmic_bytes("cluster_core_warm", items, True) == 1 * 1000 * (4 * 3 + 1)
+    assert bench.phase_algorithmic_bytes("border", items, True) == 3 * 1000 * (4 * 3 + 1)
     assert bench.phase_algorithmic_bytes("markcore", items, True) == 2 * 1000 * (4 * 3 + 4)
 
 
