@@ -1535,7 +1535,12 @@ __global__ void k_cell_label(WS ws) {
 template <int D, bool F32>
 struct BorderVisitor {
   static constexpr bool kNearestFirst = false;
-  DB_DEV bool keep_node(int, int) const { return true; }
+  // Only core points can give a label: with the node roots of this setting taken
+  // (core_nodes), a node without a core cell is not entered.
+  DB_DEV bool keep_node(int level, int idx) const {
+    return !core_nodes || W->nroot[level][idx] != kNodeNoCore;
+  }
+  bool core_nodes;
   const Work* W;
   Flat F;
   int g, pm;
@@ -1611,7 +1616,7 @@ struct BorderVisitor {
 };
 
 template <int D, bool F32, class WS>
-__global__ __launch_bounds__(kBlock) void k_border(WS ws) {
+__global__ __launch_bounds__(kBlock) void k_border(WS ws, int core_nodes) {
   ws.each_wave([&](const Work& W) {
     __shared__ int s_pref[kWavesPerBlock][kWave + 1];
     __shared__ int s_start[kWavesPerBlock][kWave];
@@ -1664,6 +1669,7 @@ __global__ __launch_bounds__(kBlock) void k_border(WS ws) {
         wave_sync();
         if (taken == 0) break;
         BorderVisitor<D, F32> v;
+        v.core_nodes = core_nodes != 0;
         v.W = &W;
         v.F = Flat{s_pref[w], s_start[w]};
         v.g = g;

@@ -344,9 +344,13 @@ void stage_cluster(const Work& W, const WS& ws, hipStream_t s, const Marks& mark
   const unsigned gw = grid_for(n, kWavesPerBlock, 4096);
   const unsigned gb = grid_for(n * W.bcp_split, kWavesPerBlock, 8192);
   const unsigned gc = grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096);
+  // whether this setting's node roots were taken (ClusterBorder then skips nodes
+  // without a core cell: which nodes have one does not change during ClusterCore)
+  bool roots_taken = false;
   auto node_roots = [&]() {
     for (int l = 1; l <= kTreeLevels; ++l)
       k_node_roots<<<grid_for(W.tree.cap[l], kWavesPerBlock, 4096), kBlock, 0, s>>>(ws, l);
+    roots_taken = true;
   };
   // a warm start that knows the previous core counts runs one pass in any dimension:
   // only cells that gained core points act (see k_bcp)
@@ -376,7 +380,7 @@ void stage_cluster(const Work& W, const WS& ws, hipStream_t s, const Marks& mark
   k_relabel_min<<<gc, kBlock, 0, s>>>(ws);
   k_cell_label<<<gp, kBlock, 0, s>>>(ws);
   mark(10);
-  if (W.sparse_mode != 1) k_border<D, F32><<<gw, kBlock, 0, s>>>(ws);
+  if (W.sparse_mode != 1) k_border<D, F32><<<gw, kBlock, 0, s>>>(ws, roots_taken ? 1 : 0);
   if (W.sparse_mode != 0)
     k_border_sparse<D, F32><<<grid_for(ceil_div(n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(ws);
   mark(11);
