@@ -247,6 +247,14 @@ const char *dbscan_phase_name(int32_t phase);
  *                          points; 1: every such instance, alone or not, of any
  *                          size; 0: never (one chain of launches per instance).
  *                          Results are the same either way.
+ *   DBSCAN_OPT_MARK_SPLIT  MarkCore waves per cell (their candidate chunks dealt out
+ *                          among them), up to 3 dimensions in grids of at least
+ *                          32 points per cell on average: 1, 2, 4 or 8 (-1:
+ *                          automatic = 4).
+ *   DBSCAN_OPT_DENSE_GROUP ClusterCore (up to 3 dimensions) takes a 64-cell group
+ *                          of neighbours cell by cell, refreshing roots before each,
+ *                          when it holds at least this many points per live cell:
+ *                          1..64 (-1: automatic = 8).
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -259,13 +267,16 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_SUBCELL_MIN 8
 #define DBSCAN_OPT_SPARSE 9
 #define DBSCAN_OPT_GROUP_CLOUDS 10
+#define DBSCAN_OPT_MARK_SPLIT 11
+#define DBSCAN_OPT_DENSE_GROUP 12
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 
 /*
  * Autotuner over the tuning options (one pass or rounds, the unit level,
  * waves per unit, sub-cell order bits and, for d <= 3, the sub-cell threshold
- * among 2048, 512 and none).  dbscan_tune() runs the given
+ * among 2048, 512 and none, MarkCore's waves per cell among 1, 2, 4 and 8, and
+ * ClusterCore's cell-by-cell threshold among 4, 8, 16 and 24).  dbscan_tune() runs the given
  * instance with the default options and then changes one option at a time
  * (two sweeps of coordinate descent; a change must be 2% faster), timing each
  * candidate as the median of three runs with HIP events on `stream`.  The best
@@ -291,6 +302,7 @@ typedef struct dbscan_tuned {
   float ms_default; /* the same with the default options */
   int32_t trials;   /* option sets timed */
   int32_t size_class; /* k: the class holds n in [2^k, 2^(k+1)) */
+  int32_t mark_split, dense_group; /* as DBSCAN_OPT_MARK_SPLIT / _DENSE_GROUP */
 } dbscan_tuned;
 int dbscan_tune(dbscan_ctx *ctx, const double *points, int64_t n, int32_t d,
                 double eps, int32_t min_pts, int32_t mode, uint8_t *core_flags,

@@ -25,7 +25,8 @@ EINTERNAL = -5
 ETOOLARGE = -6
 
 OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4, "batch_graph": 5,
-           "bcp_split": 6, "filter_max_d": 7, "subcell_min": 8, "sparse": 9, "group_clouds": 10}
+           "bcp_split": 6, "filter_max_d": 7, "subcell_min": 8, "sparse": 9, "group_clouds": 10,
+           "mark_split": 11, "dense_group": 12}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1
@@ -84,6 +85,8 @@ class Tuned(ctypes.Structure):
         ("ms_default", ctypes.c_float),
         ("trials", ctypes.c_int32),
         ("size_class", ctypes.c_int32),
+        ("mark_split", ctypes.c_int32),
+        ("dense_group", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

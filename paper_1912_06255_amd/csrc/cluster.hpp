@@ -686,8 +686,9 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
     // with a point when its own share, or the sum added so far by all of them,
     // reaches the cap, so every count is exact or at least the cap.
     static_assert((kMarkSplit & (kMarkSplit - 1)) == 0, "split must be a power of two");
-    const int sh =
-        (D <= 3 && (long long)n >= (long long)kMarkSplitMean * C) ? __builtin_ctz(kMarkSplit) : 0;
+    const int sh = (D <= 3 && (long long)n >= (long long)kMarkSplitMean * C)
+                       ? __builtin_ctz((unsigned)W.mark_split)
+                       : 0;
     const int split = 1 << sh;
     Counters tot;
     const UnitRange R = xcd_units((long long)C << sh);
@@ -1230,7 +1231,7 @@ struct BcpVisitor {
     ctr.bcp += (unsigned long long)__popcll(alive);
     if constexpr (kDensePath) {
       const int tot_pts = wave_sum(on ? s1 - s0 : 0);
-      if (tot_pts >= kDenseGroup * __popcll(alive)) {
+      if (tot_pts >= W->dense_group * __popcll(alive)) {
         dense_cells(cb, alive, hr, on ? s0 : 0, on ? s1 : 0);
         return false;
       }

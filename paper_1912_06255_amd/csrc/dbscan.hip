@@ -30,6 +30,8 @@ struct Resolved {
   int split;       // most waves per ClusterCore unit
   int fine;        // sub-cell Morton bits per dimension
   int sub;         // cells of at least this many points get sub-cell order (k_subsort); 0: none
+  int mark_split;  // MarkCore waves per cell (d <= 3, grids of kMarkSplitMean+ points per cell)
+  int dense;       // ClusterCore takes a group cell by cell from this many points per live cell
 };
 
 // One tuned choice: instances of dimension d, mode and n in [2^lg, 2^(lg+1)).
@@ -67,6 +69,8 @@ struct dbscan_ctx {
   int sparse = -1;        // -1: automatic (never: slower on every workload measured),
                           // 0: never, 1: always
   int group_clouds = -1;  // -1: automatic (groups of at least two), 0: never, 1: always
+  int mark_split = -1;    // -1: automatic (kMarkSplit)
+  int dense_group = -1;   // -1: automatic (kDenseGroup)
   // grouped batches: the scratch offset of the group area (0: none laid out), the
   // layout its descriptors were set up for, and the epoch base for the next layout
   size_t group_area_off = 0;
@@ -327,7 +331,7 @@ void stage_grid_back(const Work& W, const WS& ws, hipStream_t s, const Marks& ma
 template <int D, bool F32, class WS>
 void stage_count(const Work& W, const WS& ws, hipStream_t s, const Marks& mark) {
   if (W.sparse_mode != 1)
-    k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? kMarkSplit : 1), kWavesPerBlock, 8192),
+    k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? W.mark_split : 1), kWavesPerBlock, 8192),
                           kBlock, 0, s>>>(ws);
   if (W.sparse_mode != 0)
     k_markcore_sparse<D, F32><<<grid_for(ceil_div(W.n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(ws);
@@ -482,7 +486,7 @@ const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) 
 // Explicit options win; automatic ones come from the tuned table, else from fixed
 // rules (one pass for d <= 3, rounds above; one wave per unit).
 Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
-  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, kSubMinAuto};
+  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, kSubMinAuto, kMarkSplit, kDenseGroup};
   if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
   if (ctx->subcell_min >= 0) r.sub = ctx->subcell_min;
   if (ctx->bcp_rounds >= 0) r.rounds = ctx->bcp_rounds;
@@ -490,6 +494,8 @@ Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
   if (ctx->fine_bits >= 0) r.fine = ctx->fine_bits;
   if (ctx->bcp_split > 0) r.split = ctx->bcp_split;
   if (r.split <= 0) r.split = 1;
+  if (ctx->mark_split > 0) r.mark_split = ctx->mark_split;
+  if (ctx->dense_group > 0) r.dense = ctx->dense_group;
   return r;
 }
 
@@ -521,6 +527,8 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
   W.bcp_split = R.split;
+  W.mark_split = R.mark_split;
+  W.dense_group = R.dense;
   W.warm = 0;
   W.prev_core_count = nullptr;
   W.core_mask = 1u;
@@ -645,7 +653,8 @@ struct BatchPlan {
 
 bool same_resolved(const Resolved& a, const Resolved& b) {
   return a.rounds == b.rounds && a.unit_level == b.unit_level && a.split == b.split &&
-         a.fine == b.fine && a.sub == b.sub;
+         a.fine == b.fine && a.sub == b.sub && a.mark_split == b.mark_split &&
+         a.dense == b.dense;
 }
 
 #ifndef DB_GROUP_MAX_N
@@ -908,6 +917,8 @@ std::vector<unsigned char> batch_key(const dbscan_ctx* ctx, const dbscan_instanc
   put(k, ctx->subcell_min);
   put(k, ctx->sparse);
   put(k, ctx->group_clouds);
+  put(k, ctx->mark_split);
+  put(k, ctx->dense_group);
   put(k, count);
   for (int32_t i = 0; i < count; ++i) {
     const dbscan_instance& I = inst[i];
@@ -1212,7 +1223,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     return DBSCAN_EHIP;
   }
   // start from the fixed rules (the tuned table of this class is ignored)
-  Resolved best{d > 3 ? 1 : 0, 1, 1, 0, kSubMinAuto};
+  Resolved best{d > 3 ? 1 : 0, 1, 1, 0, kSubMinAuto, kMarkSplit, kDenseGroup};
   int err = DBSCAN_OK;
   // first run pays one-time costs (scratch growth, code loading); not timed
   rc = run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s, best);
@@ -1226,9 +1237,9 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
   // coordinate descent over the options, two sweeps; a change must win by 2%
   for (int sweep = 0; sweep < 2 && err == DBSCAN_OK; ++sweep) {
     bool changed = false;
-    for (int opt = 0; opt < 5 && err == DBSCAN_OK; ++opt) {
-      static const int kVals[5][3] = {
-          {0, 1, -1}, {1, 2, 4}, {0, 2, -1}, {0, 1, 2}, {kSubMinAuto, 512, 0}};
+    for (int opt = 0; opt < 7 && err == DBSCAN_OK; ++opt) {
+      static const int kVals[7][3] = {{0, 1, -1}, {1, 2, 4},    {0, 2, -1},      {0, 1, 2},
+                                      {kSubMinAuto, 512, 0}, {1, 2, 8}, {4, 16, 24}};
       for (int k = 0; k < 3 && err == DBSCAN_OK; ++k) {
         const int v = kVals[opt][k];
         if (v < 0) continue;
@@ -1237,10 +1248,13 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
                      : opt == 1 ? &c.split
                      : opt == 2 ? &c.fine
                      : opt == 3 ? &c.unit_level
-                                : &c.sub;
+                     : opt == 4 ? &c.sub
+                     : opt == 5 ? &c.mark_split
+                                : &c.dense;
         if (*field == v) continue;
         if (opt == 3 && !c.rounds) continue;  // the unit level only acts in rounds
         if (opt == 4 && (d > 3 || c.fine > 0)) continue;  // sub-cell order: d <= 3, no fine bits
+        if (opt >= 5 && d > 3) continue;  // MarkCore's split and the cell-by-cell path: d <= 3
         *field = v;
         const float t = time_options(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
                                      s, c, e0, e1, &err);
@@ -1274,6 +1288,8 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     out->bcp_split = best.split;
     out->fine_bits = best.fine;
     out->subcell_min = best.sub;
+    out->mark_split = best.mark_split;
+    out->dense_group = best.dense;
     out->ms = t_best;
     out->ms_default = t_default;
     out->trials = trials;
@@ -1286,10 +1302,11 @@ int dbscan_tune_save(dbscan_ctx* ctx, const char* path) {
   if (!ctx || !path) return DBSCAN_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return DBSCAN_EINVAL;
-  std::fprintf(f, "dbscan-tune 2\n");
+  std::fprintf(f, "dbscan-tune 3\n");
   for (const TunedEntry& e : ctx->tuned)
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds,
-                 e.r.unit_level, e.r.split, e.r.fine, e.r.sub, (double)e.ms);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds,
+                 e.r.unit_level, e.r.split, e.r.fine, e.r.sub, e.r.mark_split, e.r.dense,
+                 (double)e.ms);
   return std::fclose(f) == 0 ? DBSCAN_OK : DBSCAN_EINVAL;
 }
 
@@ -1299,28 +1316,37 @@ int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
   if (!f) return DBSCAN_EINVAL;
   int version = 0;
   std::vector<TunedEntry> got;
-  // version 1 has no sub-cell threshold (it reads as automatic)
-  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && (version == 1 || version == 2)
+  // version 1 has no sub-cell threshold, versions 1 and 2 no MarkCore split or
+  // cell-by-cell threshold (they read as automatic)
+  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version >= 1 && version <= 3
                ? DBSCAN_OK
                : DBSCAN_EINVAL;
   while (rc == DBSCAN_OK) {
     TunedEntry e{};
     e.r.sub = kSubMinAuto;
+    e.r.mark_split = kMarkSplit;
+    e.r.dense = kDenseGroup;
     double ms = 0.0;
-    const int want = version == 1 ? 8 : 9;
+    const int want = version == 1 ? 8 : version == 2 ? 9 : 11;
     const int k = version == 1
                       ? std::fscanf(f, "%d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg,
                                     &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine, &ms)
-                      : std::fscanf(f, "%d %d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg,
+                  : version == 2
+                      ? std::fscanf(f, "%d %d %d %d %d %d %d %d %lf", &e.d, &e.mode, &e.lg,
                                     &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine,
-                                    &e.r.sub, &ms);
+                                    &e.r.sub, &ms)
+                      : std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf", &e.d, &e.mode,
+                                    &e.lg, &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine,
+                                    &e.r.sub, &e.r.mark_split, &e.r.dense, &ms);
     if (k == EOF) break;
     const bool ok = k == want && e.d >= 1 && e.d <= DBSCAN_MAX_D &&
                     (e.mode == DBSCAN_PLAIN_FP64 || e.mode == DBSCAN_FP32_FILTER) &&
                     e.lg >= 0 && e.lg <= 62 && (e.r.rounds == 0 || e.r.rounds == 1) &&
                     e.r.unit_level >= 0 && e.r.unit_level <= kTreeLevels && e.r.split >= 1 &&
                     e.r.split <= 64 && e.r.fine >= 0 && e.r.fine <= 8 && e.r.sub >= 0 &&
-                    e.r.sub != 1;
+                    e.r.sub != 1 && (e.r.mark_split == 1 || e.r.mark_split == 2 ||
+                                     e.r.mark_split == 4 || e.r.mark_split == 8) &&
+                    e.r.dense >= 1 && e.r.dense <= 64;
     if (!ok) {
       rc = DBSCAN_EINVAL;
       break;
@@ -1529,6 +1555,14 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value < -1 || value > 1) return DBSCAN_EINVAL;
       ctx->group_clouds = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_MARK_SPLIT:
+      if (value != -1 && value != 1 && value != 2 && value != 4 && value != 8) return DBSCAN_EINVAL;
+      ctx->mark_split = (int)value;
+      return DBSCAN_OK;
+    case DBSCAN_OPT_DENSE_GROUP:
+      if (value != -1 && (value < 1 || value > 64)) return DBSCAN_EINVAL;
+      ctx->dense_group = (int)value;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -1546,6 +1580,8 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_SUBCELL_MIN: *value = ctx->subcell_min; return DBSCAN_OK;
     case DBSCAN_OPT_SPARSE: *value = ctx->sparse; return DBSCAN_OK;
     case DBSCAN_OPT_GROUP_CLOUDS: *value = ctx->group_clouds; return DBSCAN_OK;
+    case DBSCAN_OPT_MARK_SPLIT: *value = ctx->mark_split; return DBSCAN_OK;
+    case DBSCAN_OPT_DENSE_GROUP: *value = ctx->dense_group; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

@@ -74,6 +74,8 @@ struct Work {
   int force_recheck;  // filter mode: decide every pair in float64
   int count_cap;      // MarkCore counts neighbours up to this value (largest minPts of the eps)
   int bcp_split;      // waves per ClusterCore unit
+  int mark_split;     // MarkCore waves per cell (a power of two; grids of many points per cell)
+  int dense_group;    // ClusterCore takes a group cell by cell from this many points per live cell
   int sub_min;        // cells of at least this many points get sub-cell order (k_subsort); kIntMax: none
   int warm;           // ClusterCore starts from the union-find the previous setting left (a larger
                       // minPts of the same eps: its core points, hence its links, are a subset)

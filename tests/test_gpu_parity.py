@@ -365,23 +365,32 @@ def test_sub_cell_order_exact_boundaries(opts, mode, gpu_lib):
                                   dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=1),
                                   dict(bcp_split=4), dict(bcp_split=2, bcp_rounds=1),
                                   dict(sparse=0, bcp_rounds=1, unit_level=2),
-                                  dict(sparse=0, bcp_rounds=0), dict(sparse=1)])
+                                  dict(sparse=0, bcp_rounds=0), dict(sparse=1),
+                                  dict(mark_split=1), dict(mark_split=2), dict(mark_split=8),
+                                  dict(dense_group=1), dict(dense_group=64)])
 @pytest.mark.parametrize("mode", MODES)
 def test_tuning_options_do_not_change_results(opts, mode, gpu_lib):
     n = 40_000
     X = seed_spreader_3d(n, domain=1e5 * (n / 1e6) ** (1 / 3), seed=303)
     rng = np.random.Generator(np.random.PCG64(304))
     Y = gaussian_mixture(8000, 5, 10, 1.0, 12.0, 0.05, rng)
+    # dense 2D blobs: hundreds of points per cell, so MarkCore splits its cells over
+    # waves and ClusterCore takes groups cell by cell
+    Z = gaussian_mixture(20_000, 2, 4, 1.0, 40.0, 0.0, rng)  # 59 points per cell at eps 1
     wantX = dbscan_o1(X, 200.0, 10)
     wantY = dbscan_o1(Y, 2.0, 10)
+    wantZ = dbscan_o1(Z, 1.0, 400)  # 87 % core, 4 clusters
     try:
         _set_opts(**opts)
         gx = gpu_dbscan(X, 200.0, 10, mode=mode, tag=f"opts {opts} 3d")
         gy = gpu_dbscan(Y, 2.0, 10, mode=mode, tag=f"opts {opts} 5d")
+        gz = gpu_dbscan(Z, 1.0, 400, mode=mode, tag=f"opts {opts} dense 2d")
     finally:
-        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1, sparse=-1)
+        _set_opts(bcp_rounds=-1, unit_level=1, fine_bits=-1, bcp_split=-1, sparse=-1,
+                  mark_split=-1, dense_group=-1)
     assert np.array_equal(gx[0], wantX[0]) and np.array_equal(gx[1], wantX[1])
     assert np.array_equal(gy[0], wantY[0]) and np.array_equal(gy[1], wantY[1])
+    assert np.array_equal(gz[0], wantZ[0]) and np.array_equal(gz[1], wantZ[1])
 
 
 def test_option_ranges(gpu_lib):
@@ -391,7 +400,7 @@ def test_option_ranges(gpu_lib):
     bad = {"bcp_rounds": [2, -2], "unit_level": [-2, 6], "fine_bits": [-2, 9],
            "force_recheck": [2], "batch_graph": [-1], "bcp_split": [0, 65],
            "filter_max_d": [-2, 9], "subcell_min": [-2, 1], "sparse": [-2, 2],
-           "group_clouds": [-2, 2]}
+           "group_clouds": [-2, 2], "mark_split": [0, 3, 16], "dense_group": [0, 65]}
     for name, values in bad.items():
         before = binding.get_option(name)
         for v in values:

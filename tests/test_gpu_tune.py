@@ -35,6 +35,7 @@ def test_tune_then_exact(mode, clean_table):
     assert res["bcp_rounds"] in (0, 1) and 0 <= res["unit_level"] <= 5
     assert 1 <= res["bcp_split"] <= 64 and 0 <= res["fine_bits"] <= 8
     assert res["subcell_min"] in (2048, 512, 0)
+    assert res["mark_split"] in (1, 2, 4, 8) and res["dense_group"] in (4, 8, 16, 24)
     assert res["trials"] >= 4 and res["ms"] > 0 and res["ms"] <= res["ms_default"]
     assert res["size_class"] == int(np.floor(np.log2(n)))
     # the tuning runs leave the instance's exact result
@@ -59,24 +60,32 @@ def test_tune_high_dim_and_table_round_trip(clean_table, tmp_path):
     path = tmp_path / "tune.txt"
     binding.tune_save(str(path))
     lines = path.read_text().splitlines()
-    assert lines[0] == "dbscan-tune 2" and len(lines) == 2
+    assert lines[0] == "dbscan-tune 3" and len(lines) == 2
     f = lines[1].split()
-    assert [int(v) for v in f[:8]] == [5, 0, res["size_class"], res["bcp_rounds"], res["unit_level"],
-                                       res["bcp_split"], res["fine_bits"], res["subcell_min"]]
+    assert [int(v) for v in f[:10]] == [5, 0, res["size_class"], res["bcp_rounds"], res["unit_level"],
+                                        res["bcp_split"], res["fine_bits"], res["subcell_min"],
+                                        res["mark_split"], res["dense_group"]]
     binding.tune_clear()
     binding.tune_save(str(path.with_suffix(".empty")))
-    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 2"]
+    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 3"]
     binding.tune_load(str(path))
     binding.tune_save(str(path.with_suffix(".again")))
     assert path.with_suffix(".again").read_text().splitlines() == lines
 
-    # a version-1 file (no sub-cell threshold) loads, the threshold reading as automatic
+    # older files load, the options they lack reading as automatic: version 1 has no
+    # sub-cell threshold, versions 1 and 2 no MarkCore split or cell-by-cell threshold
     old = tmp_path / "v1.txt"
     old.write_text("dbscan-tune 1\n3 1 13 0 1 2 0 1.5\n")
     binding.tune_clear()
     binding.tune_load(str(old))
     binding.tune_save(str(path.with_suffix(".v1")))
-    assert path.with_suffix(".v1").read_text().splitlines() == ["dbscan-tune 2", "3 1 13 0 1 2 0 2048 1.5"]
+    assert path.with_suffix(".v1").read_text().splitlines() == ["dbscan-tune 3", "3 1 13 0 1 2 0 2048 4 8 1.5"]
+    old2 = tmp_path / "v2.txt"
+    old2.write_text("dbscan-tune 2\n2 0 12 1 1 2 0 512 0.5\n")
+    binding.tune_clear()
+    binding.tune_load(str(old2))
+    binding.tune_save(str(path.with_suffix(".v2")))
+    assert path.with_suffix(".v2").read_text().splitlines() == ["dbscan-tune 3", "2 0 12 1 1 2 0 512 4 8 0.5"]
     binding.tune_clear()
     binding.tune_load(str(path))
 
@@ -85,6 +94,10 @@ def test_tune_high_dim_and_table_round_trip(clean_table, tmp_path):
     with pytest.raises(binding.DbscanError) as e:
         binding.tune_load(str(bad))
     assert e.value.code == binding.EINVAL
+    bad3 = tmp_path / "bad3.txt"
+    bad3.write_text("dbscan-tune 3\n5 0 13 1 1 2 0 2048 3 8 1.0\n")  # MarkCore split not a power of two
+    with pytest.raises(binding.DbscanError):
+        binding.tune_load(str(bad3))
     binding.tune_save(str(path.with_suffix(".after_bad")))
     assert path.with_suffix(".after_bad").read_text().splitlines() == lines
     with pytest.raises(binding.DbscanError):
