@@ -10,7 +10,7 @@ namespace db {
 
 constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
-// by cell instead of flattening it.
+// by cell instead of flattening it (the default of Work::dense_group).
 #ifndef DB_DENSE_GROUP
 #define DB_DENSE_GROUP 8
 #endif
@@ -28,7 +28,7 @@ constexpr int kLeafCell = DB_LEAF_CELL;
 DB_DEV int leaf_min(const Work& W) {
   return W.desc->fine_bits > 0 ? kLeafCell : max(W.sub_min, kLeafCell);
 }
-// Waves per sparse cell in MarkCore (d <= 3).
+// Waves per sparse cell in MarkCore (d <= 3; the default of Work::mark_split) ...
 #ifndef DB_MARK_SPLIT
 #define DB_MARK_SPLIT 4
 #endif
