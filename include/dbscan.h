@@ -211,7 +211,7 @@ const char *dbscan_phase_name(int32_t phase);
  *                          sort key, ordering the points inside every cell
  *                          (-1: automatic = 0, else 0..8)
  *   DBSCAN_OPT_SUBCELL_MIN with DBSCAN_OPT_FINE_BITS at 0 bits, cells of at
- *                          least this many points (d <= 3) are put into
+ *                          least this many points are put into
  *                          sub-cell order after the grid is built, the leaves
  *                          of the paper's per-cell quadtree (section "Range
  *                          Counting"): MarkCore and ClusterCore then skip or
@@ -274,8 +274,8 @@ int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 
 /*
  * Autotuner over the tuning options (one pass or rounds, the unit level,
- * waves per unit, sub-cell order bits and, for d <= 3, the sub-cell threshold
- * among 2048, 512 and none, MarkCore's waves per cell among 1, 2, 4 and 8, and
+ * waves per unit, sub-cell order bits, the sub-cell threshold among 2048, 512
+ * and none and, for d <= 3, MarkCore's waves per cell among 1, 2, 4 and 8, and
  * ClusterCore's cell-by-cell threshold among 4, 8, 16 and 24).  dbscan_tune() runs the given
  * instance with the default options and then changes one option at a time
  * (two sweeps of coordinate descent; a change must be 2% faster), timing each
@@ -288,12 +288,14 @@ int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
  * call synchronises with `stream`.  Returns DBSCAN_EINVAL for n == 0 or bad
  * arguments (as dbscan()), or the first error of a run.
  *
- * dbscan_tune_save() writes the table as text ("dbscan-tune 2", then one line
- * "d mode k rounds unit_level split fine_bits subcell_min ms" per class);
- * dbscan_tune_load() merges such a file into the table (also the earlier
- * "dbscan-tune 1" files, whose lines lack subcell_min; a malformed file leaves
- * the table unchanged and returns DBSCAN_EINVAL); dbscan_tune_clear() empties
- * it.  None of the three touches the GPU.
+ * dbscan_tune_save() writes the table as text ("dbscan-tune 4", then one line
+ * "d mode k rounds unit_level split fine_bits subcell_min mark_split
+ * dense_group ms" per class); dbscan_tune_load() merges such a file into the
+ * table (also the earlier versions: 1 lacks subcell_min, 1 and 2 lack
+ * mark_split and dense_group, and up to 3 the subcell_min of d > 3 was unused;
+ * all of these read as automatic; a malformed file leaves the table unchanged
+ * and returns DBSCAN_EINVAL); dbscan_tune_clear() empties it.  None of the
+ * three touches the GPU.
  */
 typedef struct dbscan_tuned {
   int32_t bcp_rounds, unit_level, bcp_split, fine_bits; /* the chosen options */

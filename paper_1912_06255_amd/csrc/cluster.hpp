@@ -10,7 +10,8 @@ namespace db {
 
 constexpr int kNodeNoCore = -2;
 // Mean points per live neighbour cell from which ClusterCore handles a group cell
-// by cell instead of flattening it (the default of Work::dense_group).
+// by cell instead of flattening it, up to 3 dimensions (the default of
+// Work::dense_group).
 #ifndef DB_DENSE_GROUP
 #define DB_DENSE_GROUP 8
 #endif
@@ -472,7 +473,8 @@ struct Counters {
 // eps in neighbour cells; it stops as soon as minPts is reached (early exit; the
 // result is the same as counting everything).
 // ---------------------------------------------------------------------------
-template <int D, bool F32>
+// LEAF: the sub-cell (chunk-box) path is compiled in; see k_markcore_leaf.
+template <int D, bool F32, bool LEAF>
 struct MarkCoreVisitor {
   static constexpr bool kNearestFirst = true;
   DB_DEV bool keep_node(int, int) const { return true; }
@@ -603,7 +605,7 @@ struct MarkCoreVisitor {
     wave_sync();
     const int rcs = __shfl(cs, src, kWave), rcn = __shfl(cn, src, kWave);
     bool big = false;
-    if constexpr (D <= 3) {
+    if constexpr (LEAF) {
       big = rcn >= lm;
       for (uint64_t bm = ballot(big); bm; bm &= bm - 1) {
         const int r = __ffsll((long long)bm) - 1;
@@ -666,10 +668,8 @@ struct MarkCoreVisitor {
 // Neighbour counts, capped at count_cap (the largest minPts run with this eps, so
 // that one count serves every minPts).  A cell with at least count_cap points
 // needs no test: all its points are pairwise within eps.
-template <int D, bool F32, class WS>
-// four waves per SIMD up to 3 dimensions (without the bound the float32
-// instantiation settles one register above that limit)
-__global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
+template <int D, bool F32, bool LEAF, class WS>
+DB_DEV void markcore_body(const WS& ws) {
   ws.each_wave([&](const Work& W) {
     __shared__ int s_pref[kWavesPerBlock][kWave + 1];
     __shared__ int s_start[kWavesPerBlock][kWave];
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
       q.E2 = W.E2;
       load_box<D>(W.tree, g, q);
       for (int ps = s; ps < e; ps += kWave) {
-        MarkCoreVisitor<D, F32> v;
+        MarkCoreVisitor<D, F32, LEAF> v;
         v.W = &W;
         v.F = Flat{s_pref[w], s_start[w]};
         v.order = s_order[w];
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
           v.p[d] = 0.0;
           v.ap[d] = 0.0f;
         }
-        v.lm = D <= 3 ? leaf_min(W) : kIntMax;
+        v.lm = LEAF ? leaf_min(W) : kIntMax;
         if (lane < v.pm) {
           if constexpr (F32) load_local<D>(W.X32, n, ps + lane, v.ap);
           if (!F32 || v.lm != kIntMax) load_point<D>(W.X, n, ps + lane, v.p);
@@ -741,6 +741,20 @@ __global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
     }
     tot.wave_flush(W.desc);
   });
+}
+
+// Up to 3 dimensions with the sub-cell path; four waves per SIMD there (without the
+// bound the float32 instantiation settles one register above that limit).
+template <int D, bool F32, class WS>
+__global__ __launch_bounds__(kBlock, D <= 3 ? 4 : 1) void k_markcore(WS ws) {
+  markcore_body<D, F32, D <= 3>(ws);
+}
+
+// Above 3 dimensions, for grids with sub-cell order: a separate kernel, so that the
+// usual one (cells of few points) keeps its register budget.
+template <int D, bool F32, class WS>
+__global__ __launch_bounds__(kBlock, 1) void k_markcore_leaf(WS ws) {
+  markcore_body<D, F32, true>(ws);
 }
 
 // Core flags of one minPts from the counts (Algorithm 2's test), the number of
@@ -944,12 +958,10 @@ __global__ __launch_bounds__(kBlock) void k_core_total(Work W) {
 // filter), and 64 x 64 tiles whose chunk boxes are farther than eps apart are
 // skipped whole.
 // ---------------------------------------------------------------------------
-template <int D, bool F32>
+// LEAF: the cell-by-cell and sub-cell paths are compiled in; see k_bcp_leaf.
+template <int D, bool F32, bool LEAF>
 struct BcpVisitor {
   static constexpr bool kNearestFirst = false;
-  // the cell-by-cell path for dense groups (low dimensions only: in higher
-  // dimensions cells hold few points and the path would only cost registers)
-  static constexpr bool kDensePath = D <= 3;
   float tin, tout;
   const Work* W;
   Flat F;
@@ -1229,9 +1241,17 @@ struct BcpVisitor {
     uint64_t alive = ballot(on);
     if (!alive) return false;
     ctr.bcp += (unsigned long long)__popcll(alive);
-    if constexpr (kDensePath) {
-      const int tot_pts = wave_sum(on ? s1 - s0 : 0);
-      if (tot_pts >= W->dense_group * __popcll(alive)) {
+    // Cell by cell: dense groups up to 3 dimensions; above, where cells mostly hold
+    // few points, only groups with a cell in sub-cell order.
+    if constexpr (LEAF) {
+      bool dense;
+      if constexpr (D <= 3) {
+        const int tot_pts = wave_sum(on ? s1 - s0 : 0);
+        dense = tot_pts >= W->dense_group * __popcll(alive);
+      } else {
+        dense = ballot(on && s1 - s0 >= leaf_min(*W)) != 0;
+      }
+      if (dense) {
         dense_cells(cb, alive, hr, on ? s0 : 0, on ? s1 : 0);
         return false;
       }
@@ -1354,16 +1374,14 @@ struct BcpVisitor {
 // round = -1: a single pass in which every core cell walks the whole tree.
 // WARM: the union-find starts from the previous setting's (see Work::warm); a
 // separate instantiation, so that the cold kernel keeps its register budget.
-template <int D, bool F32, bool WARM, class WS>
-// Four waves per SIMD where that fits without spilling (float64, d <= 4); the other
-// instantiations need more registers and would spill to scratch.
-__global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(WS ws, int round) {
+template <int D, bool F32, bool WARM, bool LEAF, class WS>
+DB_DEV void bcp_body(const WS& ws, int round) {
   ws.each_wave([&](const Work& W) {
     __shared__ int s_pref[kWavesPerBlock][kWave + 1];
     __shared__ int s_start[kWavesPerBlock][kWave];
     __shared__ uint64_t s_m[kWavesPerBlock][kTreeLevels + 2];
     __shared__ int s_cb[kWavesPerBlock][kTreeLevels + 2];
-    __shared__ double s_ub[kWavesPerBlock][BcpVisitor<D, F32>::kDensePath ? 2 * D * kWave : 1];
+    __shared__ double s_ub[kWavesPerBlock][LEAF ? 2 * D * kWave : 1];
     const int C = W.desc->n_cells;
     int cnt[kTreeLevels + 2];
     level_counts(C, cnt);
@@ -1397,7 +1415,7 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(WS ws, i
       // they test every neighbour cell, not only those of lower index.
       const bool gained_only = WARM && W.prev_core_count != nullptr;
       if (gained_only && W.coreCount[g] <= W.prev_core_count[g]) continue;
-      BcpVisitor<D, F32> v;
+      BcpVisitor<D, F32, LEAF> v;
       v.W = &W;
       v.F = Flat{s_pref[w], s_start[w]};
       v.ub = s_ub[w];
@@ -1454,6 +1472,21 @@ __global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(WS ws, i
     }
     tot.wave_flush(W.desc);
   });
+}
+
+// Up to 3 dimensions with the cell-by-cell and sub-cell paths.  Four waves per SIMD
+// where that fits without spilling (float64, d <= 4); the other instantiations need
+// more registers and would spill to scratch.
+template <int D, bool F32, bool WARM, class WS>
+__global__ __launch_bounds__(kBlock, (F32 || D > 4) ? 1 : 4) void k_bcp(WS ws, int round) {
+  bcp_body<D, F32, WARM, D <= 3>(ws, round);
+}
+
+// Above 3 dimensions, for grids with sub-cell order: a separate kernel, so that the
+// usual one (cells of few points) keeps its register budget.
+template <int D, bool F32, bool WARM, class WS>
+__global__ __launch_bounds__(kBlock, 1) void k_bcp_leaf(WS ws, int round) {
+  bcp_body<D, F32, WARM, true>(ws, round);
 }
 
 // Node roots for pruning: per node, the common root of its core cells, -1 when

@@ -65,7 +65,7 @@ struct dbscan_ctx {
   int batch_graph = 1;
   int bcp_split = -1;   // -1: automatic (1)
   int filter_max_d = -1;  // -1: automatic (3)
-  int subcell_min = -1;   // -1: automatic (kSubMinAuto for d <= 3), 0: never
+  int subcell_min = -1;   // -1: automatic (sub_auto), 0: never
   int sparse = -1;        // -1: automatic (never: slower on every workload measured),
                           // 0: never, 1: always
   int group_clouds = -1;  // -1: automatic (groups of at least two), 0: never, 1: always
@@ -310,8 +310,7 @@ void stage_grid_back(const Work& W, const WS& ws, hipStream_t s, const Marks& ma
   k_cells<D><<<tiles, kBlock, 0, s>>>(ws, 1);
   k_cell_box<D><<<gc, kBlock, 0, s>>>(ws, 1);
   k_cell_span<D><<<gc, kBlock, 0, s>>>(ws, 1);
-  if constexpr (D <= 3)
-    if (subsort && W.sub_min != kIntMax) k_subsort<D><<<kSubBlocks, kSubThreads, 0, s>>>(ws);
+  if (subsort && W.sub_min != kIntMax) k_subsort<D><<<kSubBlocks, kSubThreads, 0, s>>>(ws);
   mark(5);
   for (int l = 1; l <= 2; ++l) {
     const int64_t nodes = W.tree.cap[l];
@@ -330,9 +329,16 @@ void stage_grid_back(const Work& W, const WS& ws, hipStream_t s, const Marks& ma
 
 template <int D, bool F32, class WS>
 void stage_count(const Work& W, const WS& ws, hipStream_t s, const Marks& mark) {
-  if (W.sparse_mode != 1)
-    k_markcore<D, F32><<<grid_for((int64_t)W.n * (D <= 3 ? W.mark_split : 1), kWavesPerBlock, 8192),
-                          kBlock, 0, s>>>(ws);
+  if (W.sparse_mode != 1) {
+    const unsigned gm = grid_for((int64_t)W.n * (D <= 3 ? W.mark_split : 1), kWavesPerBlock, 8192);
+    // above 3 dimensions the sub-cell path has a kernel of its own (see k_markcore_leaf)
+    bool leaf = false;
+    if constexpr (D > 3) {
+      leaf = W.sub_min != kIntMax;
+      if (leaf) k_markcore_leaf<D, F32><<<gm, kBlock, 0, s>>>(ws);
+    }
+    if (!leaf) k_markcore<D, F32><<<gm, kBlock, 0, s>>>(ws);
+  }
   if (W.sparse_mode != 0)
     k_markcore_sparse<D, F32><<<grid_for(ceil_div(W.n, kWave), kWavesPerBlock, 4096), kBlock, 0, s>>>(ws);
   mark(7);
@@ -359,6 +365,13 @@ void stage_cluster(const Work& W, const WS& ws, hipStream_t s, const Marks& mark
   // a warm start that knows the previous core counts runs one pass in any dimension:
   // only cells that gained core points act (see k_bcp)
   auto bcp = [&](int round) {
+    if constexpr (D > 3) {
+      if (W.sub_min != kIntMax) {  // the sub-cell path's own kernel (see k_bcp_leaf)
+        if (W.warm) k_bcp_leaf<D, F32, true><<<gb, kBlock, 0, s>>>(ws, round);
+        else k_bcp_leaf<D, F32, false><<<gb, kBlock, 0, s>>>(ws, round);
+        return;
+      }
+    }
     if (W.warm) k_bcp<D, F32, true><<<gb, kBlock, 0, s>>>(ws, round);
     else k_bcp<D, F32, false><<<gb, kBlock, 0, s>>>(ws, round);
   };
@@ -483,10 +496,15 @@ const TunedEntry* find_tuned(const dbscan_ctx* ctx, int64_t n, int d, int mode) 
   return nullptr;
 }
 
+// The automatic sub-cell threshold: above 3 dimensions sub-cell order is only taken
+// when asked for (an option or a tuned entry), since cells there mostly hold few
+// points and its kernels need more registers.
+int sub_auto(int d) { return d <= 3 ? kSubMinAuto : 0; }
+
 // Explicit options win; automatic ones come from the tuned table, else from fixed
 // rules (one pass for d <= 3, rounds above; one wave per unit).
 Resolved resolve(const dbscan_ctx* ctx, int64_t n, int d, int mode) {
-  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, kSubMinAuto, kMarkSplit, kDenseGroup};
+  Resolved r{d > 3 ? 1 : 0, 1, 0, 0, sub_auto(d), kMarkSplit, kDenseGroup};
   if (const TunedEntry* e = find_tuned(ctx, n, d, mode)) r = e->r;
   if (ctx->subcell_min >= 0) r.sub = ctx->subcell_min;
   if (ctx->bcp_rounds >= 0) r.rounds = ctx->bcp_rounds;
@@ -521,9 +539,8 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.pts = points;
   W.desc = desc ? desc : ctx->desc;
   W.fine_max = R.fine;
-  // sub-cell order after the grid is built: d <= 3 (where the chunk-box paths
-  // exist) and only without sort-time fine bits
-  W.sub_min = (d <= 3 && R.fine == 0 && R.sub > 0) ? R.sub : kIntMax;
+  // sub-cell order after the grid is built, only without sort-time fine bits
+  W.sub_min = (R.fine == 0 && R.sub > 0) ? R.sub : kIntMax;
   W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
   W.bcp_split = R.split;
@@ -1223,7 +1240,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
     return DBSCAN_EHIP;
   }
   // start from the fixed rules (the tuned table of this class is ignored)
-  Resolved best{d > 3 ? 1 : 0, 1, 1, 0, kSubMinAuto, kMarkSplit, kDenseGroup};
+  Resolved best{d > 3 ? 1 : 0, 1, 1, 0, sub_auto(d), kMarkSplit, kDenseGroup};
   int err = DBSCAN_OK;
   // first run pays one-time costs (scratch growth, code loading); not timed
   rc = run_one(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id, s, best);
@@ -1253,7 +1270,7 @@ int dbscan_tune(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, dou
                                 : &c.dense;
         if (*field == v) continue;
         if (opt == 3 && !c.rounds) continue;  // the unit level only acts in rounds
-        if (opt == 4 && (d > 3 || c.fine > 0)) continue;  // sub-cell order: d <= 3, no fine bits
+        if (opt == 4 && c.fine > 0) continue;  // sub-cell order: only without fine bits
         if (opt >= 5 && d > 3) continue;  // MarkCore's split and the cell-by-cell path: d <= 3
         *field = v;
         const float t = time_options(ctx, points, n, d, eps, min_pts, mode, core_flags, cluster_id,
@@ -1302,7 +1319,7 @@ int dbscan_tune_save(dbscan_ctx* ctx, const char* path) {
   if (!ctx || !path) return DBSCAN_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return DBSCAN_EINVAL;
-  std::fprintf(f, "dbscan-tune 3\n");
+  std::fprintf(f, "dbscan-tune 4\n");
   for (const TunedEntry& e : ctx->tuned)
     std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.6g\n", e.d, e.mode, e.lg, e.r.rounds,
                  e.r.unit_level, e.r.split, e.r.fine, e.r.sub, e.r.mark_split, e.r.dense,
@@ -1317,8 +1334,10 @@ int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
   int version = 0;
   std::vector<TunedEntry> got;
   // version 1 has no sub-cell threshold, versions 1 and 2 no MarkCore split or
-  // cell-by-cell threshold (they read as automatic)
-  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version >= 1 && version <= 3
+  // cell-by-cell threshold (they read as automatic); up to version 3 the sub-cell
+  // threshold of d > 3 was not used (it reads as automatic too); version 4 has the
+  // fields of version 3
+  int rc = std::fscanf(f, "dbscan-tune %d", &version) == 1 && version >= 1 && version <= 4
                ? DBSCAN_OK
                : DBSCAN_EINVAL;
   while (rc == DBSCAN_OK) {
@@ -1339,6 +1358,7 @@ int dbscan_tune_load(dbscan_ctx* ctx, const char* path) {
                                     &e.lg, &e.r.rounds, &e.r.unit_level, &e.r.split, &e.r.fine,
                                     &e.r.sub, &e.r.mark_split, &e.r.dense, &ms);
     if (k == EOF) break;
+    if (version == 1 || (version <= 3 && e.d > 3)) e.r.sub = sub_auto(e.d);
     const bool ok = k == want && e.d >= 1 && e.d <= DBSCAN_MAX_D &&
                     (e.mode == DBSCAN_PLAIN_FP64 || e.mode == DBSCAN_FP32_FILTER) &&
                     e.lg >= 0 && e.lg <= 62 && (e.r.rounds == 0 || e.r.rounds == 1) &&

@@ -838,7 +838,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_span(WS ws, int only_if_split) 
 // turns unsafe cells into singletons, leaves their points in place).  The
 // order inside one code is arbitrary: no result depends on the order of the
 // points of a cell.  Buffers that are free at this point hold the moved points:
-// the sort's keys and indices, and the float32 coordinates (computed later).
+// the sort's keys and indices, and the float32 coordinates (computed later).  Up
+// to 3 dimensions every coordinate moves at once (one temporary per dimension);
+// above, one dimension at a time through one temporary, after each point's new
+// place is stored.  With at most kSubMaxBits code bits, a cell in 7 or 8
+// dimensions is split once per dimension: the first level of the paper's tree.
 constexpr int kSubThreads = 1024;
 constexpr int kSubUnroll = 8;
 
@@ -866,9 +870,8 @@ struct SubCode {
 template <int D, class WS>
 __global__ __launch_bounds__(kSubThreads) void k_subsort(WS ws) {
   ws.each([&](const Work& W) {
-    static_assert(D <= 3, "sub-cell order is built for d <= 3 only");
     constexpr int NW = kSubThreads / kWave;
-    constexpr int U = kSubUnroll;
+    constexpr int U = D <= 3 ? kSubUnroll : 2;
     __shared__ int s_off[1 << kSubMaxBits];
     __shared__ uint32_t s_wsum[NW];
     const GridDesc* g = W.desc;
@@ -879,6 +882,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subsort(WS ws) {
     double* tmp[3] = {reinterpret_cast<double*>(W.keyA), reinterpret_cast<double*>(W.keyB),
                       reinterpret_cast<double*>(W.X32)};
     int32_t* tperm = reinterpret_cast<int32_t*>(W.idxA);
+    int32_t* dst = reinterpret_cast<int32_t*>(W.X32);  // d > 3: each point's new place
     for (int t = blockIdx.x; t < nq; t += gridDim.x) {
       const int s = W.sublist[t];
       const int c = W.cellOf[s];
@@ -933,60 +937,98 @@ __global__ __launch_bounds__(kSubThreads) void k_subsort(WS ws) {
         }
       }
       __syncthreads();
-      // (3) every point and its input index to its place in the temporaries
-      for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
-        int pm[U];
-        double x[U][D];
+      if constexpr (D > 3) {
+        // (3) each point's new place, and its input index moved there
+        for (int i = a + tid; i < b; i += kSubThreads) {
+          double x[D];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kSubThreads;
-          const bool ok = i < b;
-          pm[u] = ok ? W.perm[i] : 0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) x[u][k] = ok ? W.X[(size_t)k * n + i] : 0.0;
+          for (int k = 0; k < D; ++k) x[k] = W.X[(size_t)k * n + i];
+          const int t = atomicAdd(&s_off[code(x)], 1);
+          dst[i] = t;
+          tperm[t] = W.perm[i];
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (i0 + u * kSubThreads >= b) continue;
-          const int t = atomicAdd(&s_off[code(x[u])], 1);
-          tperm[t] = pm[u];
-#pragma unroll
-          for (int k = 0; k < D; ++k) tmp[k][t] = x[u][k];
+        __syncthreads();
+        // (4) the coordinates, one dimension at a time through tmp[0]
+        for (int k = 0; k < D; ++k) {
+          for (int i = a + tid; i < b; i += kSubThreads) tmp[0][dst[i]] = W.X[(size_t)k * n + i];
+          __syncthreads();
+          for (int i = a + tid; i < b; i += kSubThreads) W.X[(size_t)k * n + i] = tmp[0][i];
+          __syncthreads();
         }
-      }
-      __syncthreads();
-      // (4) back into place, one wave per chunk, with the chunk's new box
-      constexpr int V = 4;
-      for (int ch0 = a / kWave + w * V; ch0 < b / kWave; ch0 += NW * V) {
-        int pm[V];
-        double x[V][D];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const int i = (ch0 + v) * kWave + lane;
-          const bool ok = i < b;
-          pm[v] = ok ? tperm[i] : 0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) x[v][k] = ok ? tmp[k][i] : 0.0;
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const int ch = ch0 + v;
-          if (ch * kWave >= b) continue;
+        // (5) the input indices and the chunks' new boxes, one wave per chunk (a and
+        // b are multiples of the chunk size)
+        for (int ch = a / kWave + w; ch < b / kWave; ch += NW) {
           const int i = ch * kWave + lane;
-          W.perm[i] = pm[v];
-          if (W.inv) W.inv[pm[v]] = i;
+          const int pm = tperm[i];
+          W.perm[i] = pm;
+          if (W.inv) W.inv[pm] = i;
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            W.X[(size_t)k * n + i] = x[v][k];
-            const double mn = wave_min(x[v][k]), mx = wave_max(x[v][k]);
+            const double x = W.X[(size_t)k * n + i];
+            const double mn = wave_min(x), mx = wave_max(x);
             if (lane == 0) {
               W.chunkLo[(size_t)k * W.chunkCap + ch] = mn;
               W.chunkHi[(size_t)k * W.chunkCap + ch] = mx;
             }
           }
         }
+        __syncthreads();
+      } else {
+        // (3) every point and its input index to its place in the temporaries
+        for (int i0 = a + tid; i0 < b; i0 += U * kSubThreads) {
+          int pm[U];
+          double x[U][D];
+  #pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kSubThreads;
+            const bool ok = i < b;
+            pm[u] = ok ? W.perm[i] : 0;
+  #pragma unroll
+            for (int k = 0; k < D; ++k) x[u][k] = ok ? W.X[(size_t)k * n + i] : 0.0;
+          }
+  #pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (i0 + u * kSubThreads >= b) continue;
+            const int t = atomicAdd(&s_off[code(x[u])], 1);
+            tperm[t] = pm[u];
+  #pragma unroll
+            for (int k = 0; k < D; ++k) tmp[k][t] = x[u][k];
+          }
+        }
+        __syncthreads();
+        // (4) back into place, one wave per chunk, with the chunk's new box
+        constexpr int V = 4;
+        for (int ch0 = a / kWave + w * V; ch0 < b / kWave; ch0 += NW * V) {
+          int pm[V];
+          double x[V][D];
+  #pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const int i = (ch0 + v) * kWave + lane;
+            const bool ok = i < b;
+            pm[v] = ok ? tperm[i] : 0;
+  #pragma unroll
+            for (int k = 0; k < D; ++k) x[v][k] = ok ? tmp[k][i] : 0.0;
+          }
+  #pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const int ch = ch0 + v;
+            if (ch * kWave >= b) continue;
+            const int i = ch * kWave + lane;
+            W.perm[i] = pm[v];
+            if (W.inv) W.inv[pm[v]] = i;
+  #pragma unroll
+            for (int k = 0; k < D; ++k) {
+              W.X[(size_t)k * n + i] = x[v][k];
+              const double mn = wave_min(x[v][k]), mx = wave_max(x[v][k]);
+              if (lane == 0) {
+                W.chunkLo[(size_t)k * W.chunkCap + ch] = mn;
+                W.chunkHi[(size_t)k * W.chunkCap + ch] = mx;
+              }
+            }
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   });
 }

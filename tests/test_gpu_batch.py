@@ -171,6 +171,32 @@ def test_batch_many_minpts_per_eps(mode, rounds, sparse, gpu_lib):
         binding.set_option("sparse", -1)
 
 
+@pytest.mark.parametrize("mode,filter_max_d", [("fp64", -1), ("fp32_filter", 8)])
+def test_batch_sub_cell_order_high_d(mode, filter_max_d, gpu_lib):
+    """Sub-cell order above 3 dimensions in a batch: settings of one eps (the warm
+    ClusterCore kernel), an eps twice as large (a grid cut from the finer one's
+    keys, regrouped again), and a 7D cloud; captured and replayed."""
+    from paper_1912_06255_amd import binding
+
+    rng = np.random.Generator(np.random.PCG64(905))
+    A = gaussian_mixture(30_000, 5, 4, 0.4, 20.0, 0.05, rng)
+    B = gaussian_mixture(20_000, 7, 3, 0.4, 15.0, 0.05, rng)
+    clouds = [A, B]
+    settings = [[(2.0, 6800), (2.0, 1000), (2.0, 10), (4.0, 7000), (1.0, 50)],
+                [(2.5, 6200), (2.5, 10)]]
+    binding.set_option("subcell_min", 2)
+    binding.set_option("filter_max_d", filter_max_d)
+    try:
+        b = _batch(clouds, settings, mode)
+        for r in range(2):
+            log(f"high-d sub-cell batch {mode} run {r}")
+            b.run()
+            _check_batch(b, clouds, settings, f"high-d sub-cell {mode} run {r}")
+    finally:
+        binding.set_option("subcell_min", -1)
+        binding.set_option("filter_max_d", -1)
+
+
 def test_batch_invalid_arguments(gpu_lib):
     import torch
 

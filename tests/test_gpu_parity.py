@@ -360,6 +360,51 @@ def test_sub_cell_order_exact_boundaries(opts, mode, gpu_lib):
         _set_opts(**_SUB_RESET)
 
 
+# Above 3 dimensions: Gaussian clusters tight enough for cells of hundreds of points
+# (d, n, components, sigma, spread, eps, minPts values).  The larger minPts sits near
+# the component sizes, so that core and non-core points mix and the counts through
+# whole chunks decide.
+_HD_SUB = [
+    (4, 30_000, 4, 0.5, 15.0, 1.5, (10, 4000)),
+    (5, 30_000, 4, 0.4, 20.0, 2.0, (10, 6800)),
+    (7, 20_000, 3, 0.4, 15.0, 2.5, (10, 6200)),
+    (8, 16_000, 2, 0.4, 12.0, 3.0, (10, 7400)),
+]
+_HD_SUB_WANT = {}
+
+
+def _hd_sub_case(i):
+    d, n, k, sig, spread, eps, mps = _HD_SUB[i]
+    rng = np.random.Generator(np.random.PCG64(900 + d))
+    X = gaussian_mixture(n, d, k, sig, spread, 0.05, rng)
+    for mp in mps:
+        if (i, mp) not in _HD_SUB_WANT:
+            _HD_SUB_WANT[(i, mp)] = dbscan_o1(X, eps, mp)
+    return X, eps, mps
+
+
+@pytest.mark.parametrize("mode,filter_max_d", [("fp64", -1), ("fp32_filter", 8)])
+@pytest.mark.parametrize("opts", [dict(subcell_min=2), dict(subcell_min=512, bcp_rounds=0),
+                                  dict(subcell_min=2, bcp_rounds=1, unit_level=0)])
+@pytest.mark.parametrize("case", range(len(_HD_SUB)))
+def test_sub_cell_order_high_d(case, opts, mode, filter_max_d, gpu_lib):
+    """Sub-cell order above 3 dimensions: the coordinates regrouped one dimension at
+    a time, and MarkCore and ClusterCore kernels of their own with the chunk-box
+    paths, in float64 and with the float32 filter taking the decisions."""
+    X, eps, mps = _hd_sub_case(case)
+    d = X.shape[1]
+    try:
+        _set_opts(filter_max_d=filter_max_d, **opts)
+        for mp in mps:
+            tag = f"{d}d sub-cell {opts} {mode} eps={eps} mp={mp}"
+            want = _HD_SUB_WANT[(case, mp)]
+            got = gpu_dbscan(X, eps, mp, mode=mode, tag=tag)
+            assert np.array_equal(got[0], want[0]), f"{tag}: core flags differ"
+            assert np.array_equal(got[1], want[1]), f"{tag}: labels differ"
+    finally:
+        _set_opts(filter_max_d=-1, bcp_rounds=-1, unit_level=-1, **_SUB_RESET)
+
+
 @pytest.mark.parametrize("opts", [dict(bcp_rounds=0), dict(bcp_rounds=1, unit_level=0),
                                   dict(bcp_rounds=1, unit_level=1), dict(bcp_rounds=1, unit_level=2),
                                   dict(fine_bits=3), dict(fine_bits=0), dict(bcp_split=1),

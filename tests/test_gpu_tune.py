@@ -60,32 +60,40 @@ def test_tune_high_dim_and_table_round_trip(clean_table, tmp_path):
     path = tmp_path / "tune.txt"
     binding.tune_save(str(path))
     lines = path.read_text().splitlines()
-    assert lines[0] == "dbscan-tune 3" and len(lines) == 2
+    assert lines[0] == "dbscan-tune 4" and len(lines) == 2
     f = lines[1].split()
     assert [int(v) for v in f[:10]] == [5, 0, res["size_class"], res["bcp_rounds"], res["unit_level"],
                                         res["bcp_split"], res["fine_bits"], res["subcell_min"],
                                         res["mark_split"], res["dense_group"]]
     binding.tune_clear()
     binding.tune_save(str(path.with_suffix(".empty")))
-    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 3"]
+    assert path.with_suffix(".empty").read_text().splitlines() == ["dbscan-tune 4"]
     binding.tune_load(str(path))
     binding.tune_save(str(path.with_suffix(".again")))
     assert path.with_suffix(".again").read_text().splitlines() == lines
 
     # older files load, the options they lack reading as automatic: version 1 has no
-    # sub-cell threshold, versions 1 and 2 no MarkCore split or cell-by-cell threshold
+    # sub-cell threshold, versions 1 and 2 no MarkCore split or cell-by-cell threshold,
+    # and up to version 3 the sub-cell threshold of d > 3 was unused
     old = tmp_path / "v1.txt"
     old.write_text("dbscan-tune 1\n3 1 13 0 1 2 0 1.5\n")
     binding.tune_clear()
     binding.tune_load(str(old))
     binding.tune_save(str(path.with_suffix(".v1")))
-    assert path.with_suffix(".v1").read_text().splitlines() == ["dbscan-tune 3", "3 1 13 0 1 2 0 2048 4 8 1.5"]
+    assert path.with_suffix(".v1").read_text().splitlines() == ["dbscan-tune 4", "3 1 13 0 1 2 0 2048 4 8 1.5"]
     old2 = tmp_path / "v2.txt"
     old2.write_text("dbscan-tune 2\n2 0 12 1 1 2 0 512 0.5\n")
     binding.tune_clear()
     binding.tune_load(str(old2))
     binding.tune_save(str(path.with_suffix(".v2")))
-    assert path.with_suffix(".v2").read_text().splitlines() == ["dbscan-tune 3", "2 0 12 1 1 2 0 512 4 8 0.5"]
+    assert path.with_suffix(".v2").read_text().splitlines() == ["dbscan-tune 4", "2 0 12 1 1 2 0 512 4 8 0.5"]
+    old3 = tmp_path / "v3.txt"
+    old3.write_text("dbscan-tune 3\n5 0 13 1 1 2 0 2048 4 8 1.0\n3 0 13 0 1 2 0 512 2 16 0.4\n")
+    binding.tune_clear()
+    binding.tune_load(str(old3))
+    binding.tune_save(str(path.with_suffix(".v3")))
+    assert path.with_suffix(".v3").read_text().splitlines() == [
+        "dbscan-tune 4", "5 0 13 1 1 2 0 0 4 8 1", "3 0 13 0 1 2 0 512 2 16 0.4"]
     binding.tune_clear()
     binding.tune_load(str(path))
 
