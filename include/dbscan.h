@@ -255,6 +255,16 @@ const char *dbscan_phase_name(int32_t phase);
  *                          of neighbours cell by cell, refreshing roots before each,
  *                          when it holds at least this many points per live cell:
  *                          1..64 (-1: automatic = 8).
+ *   DBSCAN_OPT_CELLS       how the cells are built in 2 dimensions: 0 (default,
+ *                          also -1) grid cells of side eps / sqrt(d); 1 the box
+ *                          method (section "Box Computation"): points sorted by
+ *                          x and cut into strips of width at most eps / sqrt(2),
+ *                          each strip sorted by y and cut into boxes the same
+ *                          way, both cuts by binary search and pointer jumping.
+ *                          The result does not change (it is the unique DBSCAN
+ *                          result); other dimensions ignore the option, and a
+ *                          batch builds such grids one at a time (no grouping,
+ *                          no grid cut from a finer eps).
  * dbscan_set_option() returns DBSCAN_EINVAL for an unknown option or value.
  */
 #define DBSCAN_OPT_BCP_ROUNDS 1
@@ -269,6 +279,7 @@ const char *dbscan_phase_name(int32_t phase);
 #define DBSCAN_OPT_GROUP_CLOUDS 10
 #define DBSCAN_OPT_MARK_SPLIT 11
 #define DBSCAN_OPT_DENSE_GROUP 12
+#define DBSCAN_OPT_CELLS 13
 int dbscan_set_option(dbscan_ctx *ctx, int32_t option, int64_t value);
 int dbscan_get_option(dbscan_ctx *ctx, int32_t option, int64_t *value);
 

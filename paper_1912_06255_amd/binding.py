@@ -26,7 +26,7 @@ ETOOLARGE = -6
 
 OPTIONS = {"bcp_rounds": 1, "unit_level": 2, "fine_bits": 3, "force_recheck": 4, "batch_graph": 5,
            "bcp_split": 6, "filter_max_d": 7, "subcell_min": 8, "sparse": 9, "group_clouds": 10,
-           "mark_split": 11, "dense_group": 12}
+           "mark_split": 11, "dense_group": 12, "cells": 13}
 
 PLAIN_FP64 = 0
 FP32_FILTER = 1

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 #include <cmath>
 #include <cstddef>
@@ -18,6 +19,7 @@
 #include "cluster.hpp"
 #include "membership.hpp"
 #include "sparse.hpp"
+#include "box.hpp"
 
 using namespace db;
 
@@ -71,6 +73,7 @@ struct dbscan_ctx {
   int group_clouds = -1;  // -1: automatic (groups of at least two), 0: never, 1: always
   int mark_split = -1;    // -1: automatic (kMarkSplit)
   int dense_group = -1;   // -1: automatic (kDenseGroup)
+  int cells = 0;          // 0: grid cells; 1: the box method in 2 dimensions
   // grouped batches: the scratch offset of the group area (0: none laid out), the
   // layout its descriptors were set up for, and the epoch base for the next layout
   size_t group_area_off = 0;
@@ -92,6 +95,9 @@ struct dbscan_ctx {
   hipGraphExec_t graph = nullptr;
   std::vector<unsigned char> graph_key;
 };
+
+// The box method's cells: asked for, and only in 2 dimensions.
+bool box_cells(const dbscan_ctx* ctx, int d) { return ctx->cells == 1 && d == 2; }
 
 namespace {
 
@@ -278,8 +284,59 @@ void stage_grid_derived(const Work& W, hipStream_t s, const Marks& mark, int j) 
   stage_grid_back<D, F32>(W, ws, s, mark, false);
 }
 
+// The box method's cells in 2 dimensions, for a grid built alone (see box.hpp):
+// strips by x, boxes by y inside each strip, each cut by binary search and pointer
+// jumping; the box ids are the sorted keys that k_cells cuts.  Profiling counts the
+// whole construction as the keys phase.
+template <bool F32>
+void stage_grid_box(const Work& W, const OneWork& ws, hipStream_t s, const Marks& mark, bool first) {
+  const int64_t n = W.n;
+  const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
+  const unsigned tiles = (unsigned)ceil_div(n, kTile);
+  const unsigned gp = grid_for(n, kBlock, 2048);
+  const unsigned gk = grid_for(n, kBlock, 512);
+  const unsigned nsb = (unsigned)ceil_div(n, kBoxScanItems);
+  int rounds = 1;  // 2^rounds > n: longer than any chain of parents
+  while ((int64_t{1} << rounds) <= n) ++rounds;
+  auto sort = [&]() {
+    for (int pass = 0; pass < 8; ++pass) k_sort_pass<<<tiles, kBlock, 0, s>>>(ws, pass);
+  };
+  auto cut = [&](int axis) {
+    k_box_parent<<<gp, kBlock, 0, s>>>(W, axis);
+    for (int r = 0; r < rounds; ++r) k_box_jump<<<gp, kBlock, 0, s>>>(W, r);
+    k_box_scan_sums<<<nsb, kBlock, 0, s>>>(W);
+    k_box_scan_top<<<1, kBlock, 0, s>>>(W, (int)nsb);
+    k_box_scan_out<<<nsb, kBlock, 0, s>>>(W, axis);
+  };
+  mark(0);
+  k_bbox_partial<2><<<nb, kBlock, 0, s>>>(ws, first ? 1 : 0);
+  mark(1);
+  k_box_xkeys<<<gk, kBlock, 0, s>>>(W, (int)nb);  // strips: sorted by x, then cut
+  sort();
+  cut(0);
+  k_box_reset<<<1, kBlock, 0, s>>>(W, 8);  // boxes: sorted by y, then stably by strip
+  k_box_ykeys<<<gk, kBlock, 0, s>>>(W);
+  sort();
+  k_box_reset<<<1, kBlock, 0, s>>>(W, 4);
+  k_box_skeys<<<gk, kBlock, 0, s>>>(W);
+  sort();
+  k_box_ygather<<<gp, kBlock, 0, s>>>(W);
+  cut(1);
+  mark(2);
+  mark(3);
+  k_cells<2><<<tiles, kBlock, 0, s>>>(ws, 0);
+  mark(4);
+  stage_grid_back<2, F32>(W, ws, s, mark, true);
+}
+
 template <int D, bool F32, class WS>
 void stage_grid(const Work& W, const WS& ws, hipStream_t s, const Marks& mark, bool first) {
+  if constexpr (D == 2 && std::is_same<WS, OneWork>::value) {
+    if (W.box_cells) {
+      stage_grid_box<F32>(W, ws, s, mark, first);
+      return;
+    }
+  }
   const int64_t n = W.n;
   const unsigned nb = grid_for(n, kBlock, kBBoxBlocks);
   const unsigned tiles = (unsigned)ceil_div(n, kTile);
@@ -541,6 +598,7 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.fine_max = R.fine;
   // sub-cell order after the grid is built, only without sort-time fine bits
   W.sub_min = (R.fine == 0 && R.sub > 0) ? R.sub : kIntMax;
+  W.box_cells = box_cells(ctx, d) ? 1 : 0;
   W.unit_max_level = R.unit_level;
   W.force_recheck = ctx->force_recheck;
   W.bcp_split = R.split;
@@ -584,7 +642,8 @@ struct EpsStep {
   bool keep_keys;  // a later grid of the chain is cut from this one
 };
 
-std::vector<EpsStep> eps_plan(const dbscan_instance& I) {
+// chains: false for grids that cannot be cut from a finer one (the box method)
+std::vector<EpsStep> eps_plan(const dbscan_instance& I, bool chains = true) {
   std::vector<double> es;
   for (int32_t a = 0; a < I.n_settings; ++a)
     if (std::find(es.begin(), es.end(), I.eps[a]) == es.end()) es.push_back(I.eps[a]);
@@ -597,7 +656,7 @@ std::vector<EpsStep> eps_plan(const dbscan_instance& I) {
     std::vector<std::pair<int, double>> chain;  // (exponent, eps)
     for (size_t b = a; b < es.size(); ++b) {
       int eb;
-      if (!used[b] && std::frexp(es[b], &eb) == ma) {
+      if (!used[b] && (b == a || chains) && std::frexp(es[b], &eb) == ma) {
         used[b] = 1;
         chain.push_back({eb, es[b]});
       }
@@ -610,9 +669,9 @@ std::vector<EpsStep> eps_plan(const dbscan_instance& I) {
   return plan;
 }
 
-bool plan_keeps_keys(const dbscan_instance* inst, int32_t count) {
+bool plan_keeps_keys(const dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count) {
   for (int32_t i = 0; i < count; ++i)
-    for (const EpsStep& P : eps_plan(inst[i]))
+    for (const EpsStep& P : eps_plan(inst[i], !box_cells(ctx, inst[i].d)))
       if (P.keep_keys) return true;
   return false;
 }
@@ -692,7 +751,7 @@ BatchPlan plan_batch(const dbscan_ctx* ctx, const dbscan_instance* inst, int32_t
   if (ctx->group_clouds != 0) {
     for (int32_t i = 0; i < count; ++i) {
       const dbscan_instance& I = inst[i];
-      if (I.n == 0 || I.n_settings != 1) continue;
+      if (I.n == 0 || I.n_settings != 1 || box_cells(ctx, I.d)) continue;
       if (ctx->group_clouds < 0 && I.d > 3 && I.n > kGroupMaxN) continue;
       const bool f32 = use_filter(ctx, mode, I.d);
       const Resolved R = resolve(ctx, I.n, I.d, mode);
@@ -826,7 +885,7 @@ int enqueue_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, b
     const Resolved R = resolve(ctx, I.n, I.d, mode);
     const bool rounds = R.rounds != 0;
     const int64_t n = I.n;
-    const std::vector<EpsStep> plan = eps_plan(I);
+    const std::vector<EpsStep> plan = eps_plan(I, !box_cells(ctx, I.d));
     for (size_t pi = 0; pi < plan.size(); ++pi) {
       const EpsStep& P = plan[pi];
       const double eps = P.eps;
@@ -1453,7 +1512,7 @@ int dbscan_batch(dbscan_ctx* ctx, const dbscan_instance* inst, int32_t count, in
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return DBSCAN_EHIP;
   const int slots = batch_slots(inst, count);
-  const bool keep_keys = plan_keeps_keys(inst, count);
+  const bool keep_keys = plan_keeps_keys(ctx, inst, count);
   BatchPlan plan = plan_batch(ctx, inst, count, mode, slots, keep_keys);
   (void)nmax;
   (void)dmax;
@@ -1583,6 +1642,10 @@ int dbscan_set_option(dbscan_ctx* ctx, int32_t option, int64_t value) {
       if (value != -1 && (value < 1 || value > 64)) return DBSCAN_EINVAL;
       ctx->dense_group = (int)value;
       return DBSCAN_OK;
+    case DBSCAN_OPT_CELLS:
+      if (value < -1 || value > 1) return DBSCAN_EINVAL;
+      ctx->cells = value == 1 ? 1 : 0;
+      return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }
@@ -1602,6 +1665,7 @@ int dbscan_get_option(dbscan_ctx* ctx, int32_t option, int64_t* value) {
     case DBSCAN_OPT_GROUP_CLOUDS: *value = ctx->group_clouds; return DBSCAN_OK;
     case DBSCAN_OPT_MARK_SPLIT: *value = ctx->mark_split; return DBSCAN_OK;
     case DBSCAN_OPT_DENSE_GROUP: *value = ctx->dense_group; return DBSCAN_OK;
+    case DBSCAN_OPT_CELLS: *value = ctx->cells; return DBSCAN_OK;
   }
   return DBSCAN_EINVAL;
 }

@@ -81,6 +81,7 @@ struct Work {
                       // minPts of the same eps: its core points, hence its links, are a subset)
   const int32_t* prev_core_count;  // warm: that setting's per-cell core counts (or null)
   int sparse_mode;    // 0: per-cell kernels, 1: batched sparse kernels
+  int box_cells;      // 1: the cells are the box method's (d = 2; see box.hpp)
   uint32_t core_mask; // bit of this setting in coreS (settings of one eps share one byte per point)
   int32_t* sublist;   // [n / 2 + 1] first sorted positions of the cells queued for sub-cell order
   double eps;

@@ -445,7 +445,8 @@ def test_option_ranges(gpu_lib):
     bad = {"bcp_rounds": [2, -2], "unit_level": [-2, 6], "fine_bits": [-2, 9],
            "force_recheck": [2], "batch_graph": [-1], "bcp_split": [0, 65],
            "filter_max_d": [-2, 9], "subcell_min": [-2, 1], "sparse": [-2, 2],
-           "group_clouds": [-2, 2], "mark_split": [0, 3, 16], "dense_group": [0, 65]}
+           "group_clouds": [-2, 2], "mark_split": [0, 3, 16], "dense_group": [0, 65],
+           "cells": [-2, 2]}
     for name, values in bad.items():
         before = binding.get_option(name)
         for v in values:
