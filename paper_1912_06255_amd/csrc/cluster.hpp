@@ -1025,7 +1025,7 @@ struct BcpVisitor {
     int pcell = -1;
     bool pv = false;
     load_chunk(cidx, xp, ap, pcell, pv);
-    pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2b;
+    pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2;
     uint64_t pm = ballot(pv);
     int curcell = -1;
     float off[D];
@@ -1080,7 +1080,7 @@ struct BcpVisitor {
       const uint8_t core = W->coreS[q];
       load_point<D>(W->X, W->n, q, xq);
       if constexpr (F32) load_local<D>(W->X32, W->n, q, aq);
-      valid = (core & W->core_mask) != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
+      valid = (core & W->core_mask) != 0 && box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
     }
     return valid;
   }
@@ -1114,7 +1114,7 @@ struct BcpVisitor {
     if (pcl < nchk)
       sv = (nchk <= kWave ? box_sqdist<D>(blo, bhi, ub, ub + D * kWave, kWave, pcl)
                           : box_sqdist<D>(blo, bhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl)) <=
-           W->E2b;
+           W->E2;
     return ballot(sv);
   }
 
@@ -1141,7 +1141,7 @@ struct BcpVisitor {
       const int hcl = hw + lane;
       double hd = hcl <= hc1 ? box_sqdist<D>(uq.lo, uq.hi, W->chunkLo, W->chunkHi, cap, hcl)
                              : __builtin_inf();
-      for (uint64_t hm = ballot(hd <= W->E2b); hm; hm &= hm - 1) {
+      for (uint64_t hm = ballot(hd <= W->E2); hm; hm &= hm - 1) {
         const int j = __ffsll((long long)hm) - 1;
         double xq[D];
         float aq[D];
@@ -1280,7 +1280,7 @@ struct BcpVisitor {
         }
         // points of h farther than eps from the unit's box drop out
         valid = (core & W->core_mask) != 0 && ((alive >> j) & 1ull) &&
-                box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2b;
+                box_sqdist<D>(xq, xq, uq.lo, uq.hi, 1, 0) <= W->E2;
       }
       if (!ballot(valid)) continue;
       double qlo[D], qhi[D];
@@ -1296,7 +1296,7 @@ struct BcpVisitor {
         const int pcl = pc0 + lane;
         bool sv = false;
         if (pcl < nchk)
-          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2b;
+          sv = box_sqdist<D>(qlo, qhi, W->chunkLo, W->chunkHi, W->chunkCap, c0 + pcl) <= W->E2;
         uint64_t sm = ballot(sv);
         while (sm && !stop) {
           const int b = __ffsll((long long)sm) - 1;
@@ -1309,7 +1309,7 @@ struct BcpVisitor {
           bool pv = false;
           load_chunk(cidx, xp, ap, pcell, pv);
           // points of the unit farther than eps from this chunk's box drop out
-          pv = pv && box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2b;
+          pv = pv && box_sqdist<D>(xp, xp, qlo, qhi, 1, 0) <= W->E2;
           uint64_t pm = ballot(pv);
           int curcell = -1;
           float off[D];
@@ -1420,7 +1420,10 @@ DB_DEV void bcp_body(const WS& ws, int round) {
       v.F = Flat{s_pref[w], s_start[w]};
       v.ub = s_ub[w];
       v.ub_ready = false;
-      v.uq.E2 = W.E2b;  // ClusterCore's radius (eps, or eps (1 + rho) when approximate)
+      // The walk, the point filters and the chunk masks work at eps: every pair within
+      // eps is met.  Only the pair test works at E2b (eps (1 + rho) when approximate),
+      // so an approximate run meets the same candidates and stops sooner.
+      v.uq.E2 = W.E2;
       v.tin = W.desc->tinb;
       v.tout = W.desc->toutb;
       v.one_cell = ulevel == 0;

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_bcp_sparse(WS ws) {
     const int C = W.desc->n_cells, n = W.n;
     const int w = threadIdx.x / kWave, lane = lane_id();
     const bool gained_only = WARM && W.prev_core_count != nullptr;
-    const double lim = sqrt(W.E2b);
+    const double lim = sqrt(W.E2);
     Counters tot;
     const UnitRange R = xcd_units((n + kWave - 1) / kWave);
     for (long long u = R.first; u < R.end; u += R.step) {
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_bcp_sparse(WS ws) {
         v.root = in ? uf_find(W.parent, c) : -1;
         v.hmax = wave_max(in ? c : -1);
         Query<D> qb;
-        qb.E2 = W.E2b;
+        qb.E2 = W.E2;  // candidates within eps; only the pair test uses E2b
         v.B.box(in, qb);
         walk<D>(W.tree, C, qb, v, WalkStack{s_m[w], s_cb[w], nullptr});
       }
