@@ -1015,6 +1015,11 @@ struct BcpVisitor {
   // unit's chunk cidx.  Unit points farther than eps from the box [blo, bhi], which
   // holds every valid q, drop out first.  Links the unit to h at the first pair
   // within eps and returns true.
+  // Approximate DBSCAN takes a small box whole, as the paper's approximate range
+  // count takes a quadtree cell of side at most eps rho / sqrt(d): when the box's
+  // diameter is at most eps rho / 2 and a unit core point lies within eps of it,
+  // that point is within eps (1 + rho / 2) of every valid q, so the unit and h are
+  // linked without pair tests (the margin of rho / 2 keeps rounding far from R).
   // hoff: T = fl32(A_unit - A_h) when the unit is one cell (else unused).
   DB_DEV bool tile(int cidx, int h, const double (&xq)[D], const float (&aq)[D], bool valid,
                    int q, const double (&blo)[D], const double (&bhi)[D], const float (&hoff)[D]) {
@@ -1027,6 +1032,12 @@ struct BcpVisitor {
     load_chunk(cidx, xp, ap, pcell, pv);
     pv = pv && box_sqdist<D>(xp, xp, blo, bhi, 1, 0) <= W->E2;
     uint64_t pm = ballot(pv);
+    if (pm && W->E2leaf > 0.0 && ballot(valid) && sqdist<D>(blo, bhi) <= W->E2leaf) {
+      bool linked = false;
+      if (lane == 0) linked = uf_link(W->parent, ucell, h);
+      ctr.links += ballot(linked) ? 1ull : 0ull;
+      return true;
+    }
     int curcell = -1;
     float off[D];
 #pragma unroll

@@ -592,6 +592,7 @@ void fill_work(dbscan_ctx* ctx, Work& W, const double* points, int64_t n, int d,
   W.eps = eps;
   W.E2 = eps * eps;
   W.E2b = W.E2;
+  W.E2leaf = 0.0;
   W.side = eps / std::sqrt((double)d);
   W.pts = points;
   W.desc = desc ? desc : ctx->desc;
@@ -1107,9 +1108,14 @@ int run_one(dbscan_ctx* ctx, const double* points, int64_t n, int32_t d, double 
   Work W;
   fill_work(ctx, W, points, n, d, eps, R);
   if (rho > 0.0) {
-    // approximate DBSCAN: ClusterCore links core points up to R = eps (1 + rho)
+    // approximate DBSCAN: ClusterCore links core points up to R = eps (1 + rho), and
+    // takes a leaf of diameter at most eps rho / 2 whole (see BcpVisitor::tile)
     const double r = eps * (1.0 + rho);
     W.E2b = r * r;
+    // (not for rho below 1e-6, where the margin of rho / 2 nears the rounding of the
+    // tests; such leaves would hold next to nothing anyway)
+    const double l = 0.5 * eps * rho;
+    if (rho >= 1e-6) W.E2leaf = l * l;
   }
   W.count_cap = min_pts;
   W.minPts = min_pts;

@@ -87,6 +87,8 @@ struct Work {
   double eps;
   double E2;
   double E2b;         // ClusterCore's pair test: E2, or fl(R^2), R = fl(eps fl(1 + rho)), for approximate DBSCAN
+  double E2leaf;      // approximate DBSCAN: leaves of squared diameter up to this are taken whole
+                      // (about (eps rho / 2)^2; 0 when exact)
   double side;
   const double* pts;  // input, [n][D]
   uint8_t* core_out;
