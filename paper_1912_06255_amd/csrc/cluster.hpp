@@ -509,65 +509,116 @@ struct MarkCoreVisitor {
     pending &= ~ballot(on && total >= W->count_cap);
   }
 
-  // A large neighbour cell h in sub-cell order, by its aligned 64-point chunks
-  // (the leaves of the paper's per-cell quadtree): a chunk whose box lies wholly
-  // within eps of a point adds its share of h to that point's count without tests,
-  // a chunk farther than eps is skipped, and only the others are tested.
-  DB_DEV bool leaf_cell(int h, int hs, int he) {
+  // A large neighbour cell h in sub-cell order: the leaves of the paper's per-cell
+  // quadtree are its aligned 64-point chunks, and above them the aligned groups of
+  // 64 chunks that lie inside h (k_group_box).  A group or chunk whose box lies
+  // wholly within eps of a point adds its share of h to that point's count without
+  // tests, one farther than eps is skipped, and only the others are opened: a group
+  // into its chunks, a chunk into point tests.
+  //
+  // One chunk for the lanes in `act`.
+  DB_DEV void leaf_chunk(int ch, int hs, int he, const float (&off)[D], uint64_t act) {
     const int lane = lane_id();
     const int n = W->n;
+    const int b0 = max(hs, ch * kWave), b1 = min(he, ch * kWave + kWave);
+    bool test = false;
+    if ((act >> lane) & 1ull) {
+      if (box_maxdist<D>(p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2)
+        cnt += b1 - b0;
+      else
+        test = box_sqdist<D>(p, p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2;
+    }
+    uint64_t tm = ballot(test);
+    if (tm) {
+      const int q = ch * kWave + lane;
+      const bool valid = q >= b0 && q < b1;
+      double xq[D];
+      float aq[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        xq[d] = 0.0;
+        aq[d] = 0.0f;
+      }
+      if (valid) {
+        if constexpr (F32) load_local<D>(W->X32, n, q, aq);
+        else load_point<D>(W->X, n, q, xq);
+      }
+      while (tm) {
+        const int t = __ffsll((long long)tm) - 1;
+        tm &= tm - 1;
+        bool hit;
+        if constexpr (F32) {
+          float at[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
+          hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks,
+                                W->E2);
+        } else {
+          double xp[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
+          hit = valid && sqdist<D>(xp, xq) <= W->E2;
+        }
+        const int add = __popcll(ballot(hit));
+        if (lane == t) cnt += add;
+      }
+    }
+  }
+
+  // After a step of the walk through h: points at the cap stop, the split waves'
+  // shares are published; true when every point of the wave is done.
+  DB_DEV bool leaf_step_done() {
+    pending &= ~ballot(cnt >= W->count_cap);
+    publish();
+    return !pending;
+  }
+
+  DB_DEV bool leaf_cell(int h, int hs, int he) {
+    const int lane = lane_id();
     float off[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) off[d] = 0.0f;
     if constexpr (F32) anchor_offsets<D>(W->tree, ag, h, off);
-    for (int ch = hs / kWave; ch <= (he - 1) / kWave; ++ch) {
-      if ((chunk_no++ & smask) != part) continue;
-      const int b0 = max(hs, ch * kWave), b1 = min(he, ch * kWave + kWave);
-      bool test = false;
-      if ((pending >> lane) & 1ull) {
-        if (box_maxdist<D>(p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2)
-          cnt += b1 - b0;
-        else
-          test = box_sqdist<D>(p, p, W->chunkLo, W->chunkHi, W->chunkCap, ch) <= W->E2;
-      }
-      uint64_t tm = ballot(test);
-      if (tm) {
-        const int q = ch * kWave + lane;
-        const bool valid = q >= b0 && q < b1;
-        double xq[D];
-        float aq[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          xq[d] = 0.0;
-          aq[d] = 0.0f;
+    // One pass over h's chunks.  A group wholly inside h is one share of a split:
+    // the wave that owns it tests its box and opens its chunks if it must (gact: the
+    // lanes that take them); the other waves skip it.  Chunks outside such groups
+    // are shares one by one.
+    uint64_t gact = ~0ull;
+    int gend = 0;  // end of the group being opened
+    const int c_last = (he - 1) / kWave;
+    for (int ch = hs / kWave; ch <= c_last;) {
+      const bool whole = ch % kGroupChunks == 0 && ch * kWave >= hs &&
+                         (ch + kGroupChunks) * kWave <= he;
+      if (whole) {
+        if ((chunk_no++ & smask) != part) {
+          ch += kGroupChunks;
+          continue;
         }
-        if (valid) {
-          if constexpr (F32) load_local<D>(W->X32, n, q, aq);
-          else load_point<D>(W->X, n, q, xq);
+        bool open = false;
+        if ((pending >> lane) & 1ull) {
+          const int g = ch / kGroupChunks;
+          if (box_maxdist<D>(p, W->groupLo, W->groupHi, W->groupCap, g) <= W->E2)
+            cnt += kGroupPts;
+          else
+            open = box_sqdist<D>(p, p, W->groupLo, W->groupHi, W->groupCap, g) <= W->E2;
         }
-        while (tm) {
-          const int t = __ffsll((long long)tm) - 1;
-          tm &= tm - 1;
-          bool hit;
-          if constexpr (F32) {
-            float at[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) at[d] = bcast(ap[d], t);
-            hit = filtered_hit<D>(W, valid, at, aq, off, tin, tout, ps + t, q, ctr.rechecks,
-                                  W->E2);
-          } else {
-            double xp[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) xp[d] = bcast(p[d], t);
-            hit = valid && sqdist<D>(xp, xq) <= W->E2;
-          }
-          const int add = __popcll(ballot(hit));
-          if (lane == t) cnt += add;
+        gact = ballot(open);
+        gend = ch + kGroupChunks;
+        if (leaf_step_done()) return true;
+        if (!gact) {
+          ch = gend;
+          continue;
+        }
+      } else if (ch >= gend) {
+        gact = ~0ull;
+        if ((chunk_no++ & smask) != part) {
+          ++ch;
+          continue;
         }
       }
-      pending &= ~ballot(cnt >= W->count_cap);
-      publish();
-      if (!pending) return true;
+      leaf_chunk(ch, hs, he, off, pending & gact);
+      if (leaf_step_done()) return true;
+      ++ch;
     }
     return false;
   }
@@ -1148,10 +1199,17 @@ struct BcpVisitor {
       unit_offsets(ah, hoff);
     }
     const int hc0 = hs / kWave, hc1 = (he - 1) / kWave;
-    for (int hw = hc0; hw <= hc1; hw += kWave) {
+    // windows of 64 chunks aligned to the groups of k_group_box: a group wholly inside
+    // h whose box is farther than eps from the unit's box is skipped unloaded
+    for (int hw = hc0 / kGroupChunks * kGroupChunks; hw <= hc1; hw += kGroupChunks) {
+      const int g = hw / kGroupChunks;
+      if (hw * kWave >= hs && (hw + kGroupChunks) * kWave <= he &&
+          !(box_sqdist<D>(uq.lo, uq.hi, W->groupLo, W->groupHi, W->groupCap, g) <= W->E2))
+        continue;
       const int hcl = hw + lane;
-      double hd = hcl <= hc1 ? box_sqdist<D>(uq.lo, uq.hi, W->chunkLo, W->chunkHi, cap, hcl)
-                             : __builtin_inf();
+      double hd = hcl >= hc0 && hcl <= hc1
+                      ? box_sqdist<D>(uq.lo, uq.hi, W->chunkLo, W->chunkHi, cap, hcl)
+                      : __builtin_inf();
       for (uint64_t hm = ballot(hd <= W->E2); hm; hm &= hm - 1) {
         const int j = __ffsll((long long)hm) - 1;
         double xq[D];

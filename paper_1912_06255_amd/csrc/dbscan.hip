@@ -143,6 +143,11 @@ size_t layout(char* base, int64_t n, int d, Work* W, int slots = 1, bool keep_ke
   w.chunkLo = c.take<double>((int64_t)w.chunkCap * d);
   w.chunkHi = c.take<double>((int64_t)w.chunkCap * d);
   w.runBox = c.take<double>((int64_t)w.chunkCap * d * 4);
+  // the boxes of the groups of 64 chunks live in the run boxes' room, which is free
+  // once the cell boxes are built (see k_group_box)
+  w.groupCap = (int)ceil_div(w.chunkCap, kGroupChunks);
+  w.groupLo = w.runBox;
+  w.groupHi = w.runBox + (size_t)w.groupCap * d;
   w.perm = c.take<int32_t>(n);
   w.cellOf = c.take<int32_t>(n);
   w.cellStart = c.take<int32_t>(n + 1);
@@ -368,6 +373,8 @@ void stage_grid_back(const Work& W, const WS& ws, hipStream_t s, const Marks& ma
   k_cell_box<D><<<gc, kBlock, 0, s>>>(ws, 1);
   k_cell_span<D><<<gc, kBlock, 0, s>>>(ws, 1);
   if (subsort && W.sub_min != kIntMax) k_subsort<D><<<kSubBlocks, kSubThreads, 0, s>>>(ws);
+  if (W.sub_min != kIntMax)
+    k_group_box<D><<<grid_for(ceil_div(n, kGroupPts), kWavesPerBlock, 1024), kBlock, 0, s>>>(ws);
   mark(5);
   for (int l = 1; l <= 2; ++l) {
     const int64_t nodes = W.tree.cap[l];

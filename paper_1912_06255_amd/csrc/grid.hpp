@@ -51,6 +51,10 @@ constexpr int kIntMax = 0x7fffffff;
 constexpr int kSubMinAuto = 2048;
 constexpr int kSubBlocks = 256;
 constexpr int kSubMaxBits = 12;
+// Groups of sub-cell leaves: 64 chunks of 64 sorted positions (k_group_box).
+constexpr int kGroupChunks = 64;
+constexpr int kGroupPts = kGroupChunks * kWave;
+static_assert(kGroupChunks == kWave, "a group's chunks are one per lane of a wave");
 
 // Look-back epoch slots within one call: 0..7 radix passes, 8..9 cell scans.
 constexpr uint32_t kEpochSlots = 16;
@@ -111,6 +115,9 @@ struct Work {
   double* runBox;     // [4][D][chunkCap] boxes of each chunk's first and last cell runs
                       // (first lo, first hi, last lo, last hi)
   int chunkCap;
+  double* groupLo;    // [D][groupCap] boxes of the aligned groups of 64 chunks (k_group_box;
+  double* groupHi;    // in the room of runBox, which is free by then)
+  int groupCap;
   int32_t* perm;      // sorted position -> input index
   int32_t* inv;       // input index -> sorted position (kept only when several settings share a grid)
   uint64_t* pk;       // [n] with inv: cell << 8 | core bits of each sorted position (one word for
@@ -1031,6 +1038,35 @@ __global__ __launch_bounds__(kSubThreads) void k_subsort(WS ws) {
           }
         }
         __syncthreads();
+      }
+    }
+  });
+}
+
+// The level above the sub-cell leaves: boxes of the aligned groups of 64 chunks
+// (4,096 sorted positions).  A group that lies inside one cell is a node of that
+// cell's tree holding 4,096 of its points: MarkCore counts or skips it whole, and
+// ClusterCore skips its chunks when its box is farther than eps.  Groups that span
+// cells are never used.  One wave per group; built after the last change to the
+// chunk boxes (sub-cell order), only where the leaves are used.
+template <int D, class WS>
+__global__ __launch_bounds__(kBlock) void k_group_box(WS ws) {
+  ws.each_wave([&](const Work& W) {
+    const int nch = (W.n + kWave - 1) / kWave;
+    const int ng = (nch + kGroupChunks - 1) / kGroupChunks;
+    const int lane = lane_id();
+    const int nw = gridDim.x * (blockDim.x / kWave);
+    for (int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; g < ng; g += nw) {
+      const int ch = g * kGroupChunks + lane;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double lo = ch < nch ? W.chunkLo[(size_t)k * W.chunkCap + ch] : __builtin_inf();
+        const double hi = ch < nch ? W.chunkHi[(size_t)k * W.chunkCap + ch] : -__builtin_inf();
+        const double a = wave_min(lo), b = wave_max(hi);
+        if (lane == 0) {
+          W.groupLo[(size_t)k * W.groupCap + g] = a;
+          W.groupHi[(size_t)k * W.groupCap + g] = b;
+        }
       }
     }
   });
